@@ -1,0 +1,161 @@
+#!/usr/bin/env python3
+"""Benchmark of the porous-media MRT lattice Boltzmann step on one MI355X.
+
+Workload (the roofline run): 4096 x 4096 side-heated porous cavity, per-node porosity
+phi ~ U[0.3, 0.9] (seeded), Kozeny-Carman permeability with mean Da = 1e-3, Ra = 1e6, Pr = 0.71,
+FP32, inputs resident in HBM before timing.  A step is one fused time step of every node
+(pull streaming, wall reconstruction, macroscopics, flow and thermal MRT collision).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-extras]
+
+Prints one JSON line.  ``value`` is MLUPS (million lattice-node updates per second).  The
+``roofline`` object prices the step kernel against HBM at its algorithmic bytes per node
+update (14 populations read + 14 written + phi and K read: 30 values, 120 B in FP32);
+``cpu_baseline`` times the FP64 CPU oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+BYTES_PER_NODE_FP32 = 30 * 4   # 14 + 14 populations, phi, K
+BYTES_PER_NODE_FP32_UNIFORM = 28 * 4
+BYTES_PER_NODE_FP64_UNIFORM = 28 * 8
+# Profiled counters of the step kernel (FETCH_SIZE + WRITE_SIZE per launch, scaled by the
+# copy-kernel calibration); None until a profile of the current kernel is recorded.
+MEASURED_TRAFFIC_BYTES = None
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--n", type=int, default=4096, help="grid side of the roofline workload")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true", help="skip batched / adjoint / FP64 legs")
+    ap.add_argument("--calib-copy", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration)")
+    return ap.parse_args()
+
+
+def timed_steps(cav, steps, torch):
+    """Time `steps` steps with HIP events on the stream the kernels run on."""
+    s = torch.cuda.current_stream()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(s)
+    cav.step(steps)
+    end.record(s)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / 1e3
+
+
+def cpu_baseline(w, budget_s=15.0):
+    """FP64 CPU oracle on the same 4096^2 workload, as many whole steps as fit the budget."""
+    import numpy as np
+    from oracle import ref
+    cores = len(os.sched_getaffinity(0))
+    ref.set_threads(cores)
+    lat = ref.RefLattice(phi=w["phi"], K=w["K"], **w["params"])
+    t0 = time.perf_counter()
+    lat.step(1)
+    t1 = time.perf_counter() - t0
+    steps = max(1, min(50, int(budget_s / max(t1, 1e-6))))
+    t0 = time.perf_counter()
+    lat.step(steps)
+    dt = time.perf_counter() - t0
+    n = w["params"]["nx"] * w["params"]["ny"]
+    lat.close()
+    del np
+    return {"value": round(n * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{steps} FP64 steps of the full {w['params']['nx']}^2 workload "
+                      f"(after 1 untimed step), {dt:.1f} s"}
+
+
+def calib_copy(mib, torch):
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes_read": n * 4, "calib_copy_bytes_written": n * 4,
+                      "launches": 5}), flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(see the sharding design notes); rerun with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1308_2071_amd import Cavity, workloads
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calib_copy:
+        calib_copy(args.calib_copy, torch)
+        return
+
+    w = workloads.roofline4096(args.n)
+    nx, ny = w["params"]["nx"], w["params"]["ny"]
+    nodes = nx * ny
+    phi32 = torch.tensor(w["phi"], dtype=torch.float32)
+    K32 = torch.tensor(w["K"], dtype=torch.float32)
+    cav = Cavity(dict(w["params"], dtype="fp32"), phi=phi32, K=K32)
+    print(f"# workload {nx}x{ny} FP32, warmup {args.warmup}", file=sys.stderr, flush=True)
+    if args.warmup:
+        cav.step(args.warmup)
+    torch.cuda.synchronize()
+    secs = timed_steps(cav, args.steps, torch)
+    obs = cav.observables(fields=False)
+    ms = secs / args.steps * 1e3
+    mlups = nodes * args.steps / secs / 1e6
+    achieved = BYTES_PER_NODE_FP32 * nodes / (secs / args.steps) / 1e9
+    print(f"# timed {args.steps} steps: {ms:.4f} ms/step, {mlups:.0f} MLUPS, "
+          f"{achieved:.0f} GB/s", file=sys.stderr, flush=True)
+    result = {
+        "metric": "coupled MRT-LB MLUPS & % HBM peak; batched and adjoint vs plain, same GPU",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"porous cavity {nx}x{ny}, per-node phi~U[0.3,0.9], "
+                               "Kozeny-Carman K (mean Da 1e-3), Ra 1e6, Pr 0.71",
+                   "nx": nx, "ny": ny, "global_batch": 1, "parallelism": "none"},
+        "hbm_pct": round(100.0 * achieved / HBM_PEAK_GBS, 2),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": MEASURED_TRAFFIC_BYTES,
+                     "bytes_per_node": BYTES_PER_NODE_FP32, "kernel": "step_kernel<float,true>"},
+        "nu_hot": obs["nu_hot"], "diverged": obs["diverged"],
+    }
+    cav.close()
+    del cav
+    torch.cuda.empty_cache()
+    if not args.no_cpu:
+        print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(result), flush=True)
+    del np
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * lbm.h -- C ABI of liblbmpm.so, the MI355X (gfx950) implementation of the coupled D2Q9 flow /
+ * D2Q5 temperature multiple-relaxation-time lattice Boltzmann model for convection heat transfer
+ * in porous media at the REV scale (Q. Liu, Y.-L. He, Q. Li, W.-Q. Tao, arXiv:1308.2071).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every function returns an lbm_status; nothing throws or aborts across the ABI.  A failed
+ *    call leaves a human-readable message in lbm_last_error() (thread-local).
+ *  - Argument checking happens before any device call, so LBM_E_INVAL never leaves work queued.
+ *  - Device memory is owned by the caller.  The library never allocates device memory: the
+ *    caller passes a workspace of at least lbm_workspace_size() bytes (256-byte aligned) that
+ *    stays valid until lbm_destroy().  Host memory for the context itself is malloc'd.
+ *  - All device work is enqueued on the caller's HIP stream (a hipStream_t passed as void*;
+ *    NULL = the null stream).  lbm_step is asynchronous; lbm_observables, lbm_grad, lbm_save
+ *    and lbm_load synchronise the stream before returning.
+ *  - Asynchronous HIP faults surface as LBM_E_HIP at the next synchronising call.
+ *  - A context is used by one host thread at a time.
+ *  - Fields are row-major [ny][nx] (x fastest), one value per lattice node, wall nodes included;
+ *    node (x, y) sits at x*dx, y*dx with dx = dt = 1 (Sec. 4).
+ *
+ * State semantics
+ * ---------------
+ *  The state between steps is the post-collision population field.  One time step is
+ *  streaming (Eqs. (18), (35)) -> non-equilibrium extrapolation at wall nodes (Sec. 4, the
+ *  paper's ref. [43]) -> macroscopic recovery (Eqs. (36), (22), (21), (23), (4)) -> collision in
+ *  moment space (Eqs. (17), (34)).  Observables at time n are the macroscopic fields after the
+ *  n-th streaming and wall reconstruction.  At n = 0 every post-collision population is at
+ *  rest equilibrium, f_i = w_i rho0 and g_i = wt_i T_init (Eq. (13) with u = 0 and
+ *  phi*p = rho0 cs^2; Eq. (37a) with u = 0).
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lbm_status;
+#define LBM_OK 0
+#define LBM_E_INVAL (-1)       /* bad argument; nothing was enqueued                        */
+#define LBM_E_NOMEM (-2)       /* workspace too small, or host allocation failed            */
+#define LBM_E_HIP (-3)         /* a HIP call failed (launch, copy, or an earlier async fault) */
+#define LBM_E_DIVERGED (-4)    /* a field is not finite or |u| exceeds cs; state still readable */
+#define LBM_E_STATE (-5)       /* call not valid in the context's current state             */
+#define LBM_E_UNSUPPORTED (-6) /* valid request this build does not implement               */
+
+/* Arithmetic of the populations and of every per-node operation. */
+#define LBM_FP32 0
+#define LBM_FP64 1
+
+/* Side conditions (Sec. 4.1, Fig. 1).  Velocity is no-slip on every non-periodic side.
+ * Periodic sides come in pairs (west with east, south with north). */
+#define LBM_WALL_ISOTHERMAL 0
+#define LBM_WALL_ADIABATIC 1
+#define LBM_PERIODIC 2
+
+/* Sides, in the order of lbm_params.bc and T_wall. */
+#define LBM_WEST 0
+#define LBM_EAST 1
+#define LBM_SOUTH 2
+#define LBM_NORTH 3
+
+/* Problem statement of Sec. 2 and Sec. 4.  Defaults (lbm_default_params) are the paper's:
+ * rho0 = 1, varpi = -2, J = 1, sigma = 1, Ma = 0.1, s_e = s_eps = 1.1, s_q = 1.2,
+ * zeta3 = zeta4 = 1.5 (Sec. 4), hot west wall T = 1, cold east wall T = 0, adiabatic south and
+ * north walls (Sec. 4.1), T_init = 0.5. */
+typedef struct {
+    int32_t nx, ny;          /* lattice nodes including wall nodes; L = nx - 1              */
+    int32_t bc[4];           /* LBM_WALL_ISOTHERMAL / LBM_WALL_ADIABATIC / LBM_PERIODIC      */
+    double T_wall[4];        /* wall temperature where bc == LBM_WALL_ISOTHERMAL             */
+    double Ra, Pr, Da, J;    /* Rayleigh, Prandtl, Darcy numbers, viscosity ratio (Sec. 2)  */
+    double Ma, sigma, varpi, rho0; /* Mach number, heat capacity ratio, Eq. (29) constant, rho0 */
+    double s_e, s_eps, s_q;  /* relaxation rates s1, s2, s4 = s6 of Eq. (20)                  */
+    double zeta3, zeta4;     /* relaxation rates zeta3, zeta4 of Eq. (31)                     */
+    int32_t forchheimer;     /* 1: F_phi = 1.75/sqrt(150 phi^3) (Eq. (5)); 0: F_phi = 0        */
+    double T_init;           /* initial temperature of every node                            */
+    double ext_accel[2];     /* extra body acceleration added to G of Eq. (4) (0 by default)  */
+    double tau_v, tau_T;     /* > 0 overrides Eq. (37b); otherwise derived from Ma, Ra, Pr, J */
+    double gbeta;            /* >= 0 overrides g*beta; negative: Ma^2 cs^2 / (dT L)           */
+    int32_t dtype;           /* LBM_FP32 or LBM_FP64                                          */
+    int32_t checkpoint_every;/* 0: no adjoint tape; C > 0: checkpoint every C steps, lbm_grad on */
+} lbm_params;
+
+/* Observables at the current time level. */
+typedef struct {
+    double nu_hot;    /* average Nusselt number of the west wall, Eq. (38)                     */
+    double nu_cold;   /* average Nusselt number of the east wall, Eq. (38)                     */
+    double max_speed; /* max |u| over the lattice                                              */
+    double mass_err;  /* |sum f - n rho0| / (n rho0) over the stored post-collision populations */
+    int64_t step;     /* time level n                                                          */
+    int32_t diverged; /* 1 when a field is not finite or max |u| exceeds cs = 1/sqrt(3)        */
+    int32_t pad_;
+} lbm_obs;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Fill *p with the paper's defaults (Sec. 4) for a 64 x 64 side-heated cavity at Ra = 1e3,
+ * Pr = 1, Da = 1e-2, FP32, no tape. */
+lbm_status lbm_default_params(lbm_params* p);
+
+/* Derived parameters of Sec. 4 for *p, in this order:
+ *  out[0] L = nx - 1, out[1] tau_v (Eq. (37b)), out[2] tau_T (Eq. (37b) with nu = nu_e / J, so
+ *  that Pr = nu / alpha_e and alpha_e = sigma csT^2 (tau_T - 1/2), Eq. (A9)), out[3] nu_e
+ *  (Eq. (24)), out[4] nu, out[5] g*beta (Ma = U / cs, U = sqrt(g beta dT L)), out[6] dT,
+ *  out[7] T0, out[8] K = Da L^2 (infinite when Da <= 0).  out has room for 9 doubles. */
+lbm_status lbm_derived(const lbm_params* p, double* out);
+
+/* Bytes of device workspace lbm_init needs for *p; with checkpoint_every > 0 the adjoint tape
+ * for up to nsteps_max time steps is included. */
+lbm_status lbm_workspace_size(const lbm_params* p, int64_t nsteps_max, size_t* bytes);
+
+/* Create a cavity.  phi and K are device arrays [ny][nx] of p->dtype holding the porosity phi
+ * (0 < phi <= 1) and permeability K (> 0) of each node (Eqs. (4), (5)); either may be NULL:
+ * phi then takes phi_uniform everywhere, K takes Da L^2 everywhere (no Darcy or Forchheimer
+ * drag when Da <= 0).  The library copies them into the workspace; the caller may free them
+ * after the call returns.  The cavity starts at rest (see State semantics).
+ * Errors: LBM_E_INVAL for nx or ny below 5 on a walled axis (the five-point stencil of
+ * Eq. (38) needs five nodes) or below 2 on a periodic one, unpaired periodic sides, a
+ * derived tau_v or tau_T not above 1/2, phi_uniform outside (0, 1], varpi >= 1 (Eq. (29)),
+ * rho0, sigma or J not positive, unknown dtype or bc; LBM_E_NOMEM when ws_bytes is too
+ * small; LBM_E_HIP when a device call fails. */
+lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const void* phi, const void* K,
+                    double phi_uniform, void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* Advance by nsteps time steps (asynchronous).  With a tape, the total number of steps since
+ * lbm_init may not exceed the nsteps_max the workspace was sized for (LBM_E_STATE). */
+lbm_status lbm_step(lbm_ctx* c, int64_t nsteps);
+
+/* Observables at the current time level (synchronises).  ux, uy, p, T are optional device
+ * arrays [ny][nx] of the context's dtype receiving u (Eq. (21)), p (Eq. (23); at wall nodes
+ * phi_b p_b = phi_f p_f), T (Eq. (36)).  Returns LBM_E_DIVERGED with o->diverged = 1 when a
+ * field is not finite or max |u| exceeds cs. */
+lbm_status lbm_observables(lbm_ctx* c, lbm_obs* o, void* ux, void* uy, void* p, void* T);
+
+/* Discrete adjoint (synchronises).  For J = nu_hot at the current time level n (Eq. (38)),
+ * computes dJ_dphi = dJ * dJ/dphi(x) and dJ_dK = dJ * dJ/dK(x) at every node, the exact
+ * derivative of the n-step discrete map from rest (phi held fixed for dK, K for dphi).  Both
+ * outputs are device FP64 arrays [ny][nx]; either may be NULL.  Needs checkpoint_every > 0
+ * (else LBM_E_STATE).  The forward state is left unchanged.  Uses the checkpoints written by
+ * lbm_step and recomputes each segment between checkpoints. */
+lbm_status lbm_grad(lbm_ctx* c, double dJ, void* dJ_dphi, void* dJ_dK);
+
+/* Size in bytes of a saved state (populations plus the step counter). */
+lbm_status lbm_state_size(const lbm_ctx* c, size_t* bytes);
+
+/* Copy the state to / from host memory (synchronises).  A loaded state resumes exactly where
+ * the saved one stopped.  lbm_load on a context with a tape returns LBM_E_UNSUPPORTED. */
+lbm_status lbm_save(lbm_ctx* c, void* host_buf, size_t bytes);
+lbm_status lbm_load(lbm_ctx* c, const void* host_buf, size_t bytes);
+
+/* Release the host context (synchronises; the workspace remains the caller's). */
+lbm_status lbm_destroy(lbm_ctx* c);
+
+/* ---------------------------------------------------------------------------------------- */
+/* Batched form: many independent cavities of uneven size and parameters stepped together.   */
+/* Every cavity is the model above with its own lbm_params (all of one dtype, no tape) and    */
+/* uniform phi (phi_uniform[i]) and K = Da L^2.                                               */
+/* ---------------------------------------------------------------------------------------- */
+
+lbm_status lbm_batch_workspace_size(int32_t n, const lbm_params* p, size_t* bytes);
+
+/* Create a batch of n cavities.  tune_cache_path: file where the launch shape picked by the
+ * autotuner is cached per (device, dtype, cavity set); NULL disables tuning (default shape). */
+lbm_status lbm_batch_init(lbm_ctx** out, int32_t n, const lbm_params* p,
+                          const double* phi_uniform, void* workspace, size_t ws_bytes,
+                          void* hip_stream, const char* tune_cache_path);
+
+/* Advance every cavity by nsteps (asynchronous; replayed from a captured HIP graph). */
+lbm_status lbm_batch_step(lbm_ctx* c, int64_t nsteps);
+
+/* Observables of every cavity (synchronises); o has n entries. */
+lbm_status lbm_batch_observables(lbm_ctx* c, lbm_obs* o);
+
+/* Launch shape in use: out[0] nodes per work-item along x, out[1] work-group size,
+ * out[2] work-groups per step, out[3] steps per graph replay. */
+lbm_status lbm_batch_shape(const lbm_ctx* c, int32_t* out);
+
+/* Human-readable name of a status code. */
+const char* lbm_status_string(lbm_status s);
+
+/* Detail of the last failure on this thread ("" when none). */
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

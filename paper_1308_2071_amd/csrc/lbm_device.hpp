@@ -1,0 +1,305 @@
+// lbm_device.hpp -- per-node arithmetic of the coupled D2Q9 / D2Q5 porous-media MRT lattice
+// Boltzmann step (Liu, He, Li, Tao, arXiv:1308.2071), shared by the plain, batched and adjoint
+// kernels.
+//
+// Storage: populations are kept as deviations from the rest state, f'_i = f_i - w_i rho0 and
+// g'_i = g_i - wt_i T0 (T0 the buoyancy reference temperature).  Every operation of the step
+// is affine in the populations, so the step is computed on deviations exactly; in FP32 this
+// keeps ~7 significant digits on the O(Ma^2) physics instead of on the O(1) rest values.
+// With deviations, m' = M f' and the rest moments rho0 (1, -2, 1, 0, ..., 0) drop out; the
+// pressure enters through P = phi p - rho0 cs^2.
+//
+// Layout: 14 planes [f0..f8, g0..g4], each [ny][pitch] with x fastest.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int kPlanes = 14;
+// 1.75 / sqrt(150): Eq. (5) gives phi F_phi = 1.75/sqrt(150) * phi^(-1/2).
+constexpr double kErgun = 0.14288690166235207;
+
+struct Geo {
+    int nx, ny, pitch;
+    int plane;             // elements per plane, ny * pitch
+    int wallW, wallE, wallS, wallN;  // side is a wall (not periodic)
+};
+
+template <typename R>
+struct Phys {
+    R rho0, inv_rho0;
+    R gbeta, ax, ay;       // g*beta and the extra body acceleration (Eq. (4), G)
+    R nu;                  // fluid viscosity in the Darcy term of Eq. (4)
+    R s_e, s_eps, s_q, s_v;        // Eq. (20)
+    R os_e, os_eps, os_q, os_v;    // 1 - s/2
+    R z_T, z3, z4;                 // Eq. (31): zeta1 = zeta2 = z_T
+    R inv_sigma, varpi;
+    R wt0, wt1;            // Eq. (37a) weights
+    R u_coef;              // 1 / (sigma csT^2)
+    R T0;
+    R theta_wall[4];       // T_wall - T0 per side
+    int iso[4];            // side is isothermal
+    int forch;             // Forchheimer term on
+    // uniform medium (used when there are no per-node planes)
+    R phi, inv_phi, c_lin, c_nl;
+};
+
+// Medium coefficients of one node: phi, 1/phi, c_lin = phi nu / K, c_nl = phi F_phi / sqrt(K).
+template <typename R>
+struct Med {
+    R phi, inv_phi, c_lin, c_nl;
+};
+
+// Macroscopic state of one node: theta = T - T0, u, P = phi p - rho0 cs^2, F (Eq. (4)).
+template <typename R>
+struct Mac {
+    R theta, ux, uy, P, Fx, Fy;
+};
+
+__device__ __forceinline__ float rsq(float x) { return __frsqrt_rn(x); }
+__device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+
+template <typename R>
+__device__ __forceinline__ Med<R> medium_from(R phi, R K, const Phys<R>& P) {
+    Med<R> m;
+    const R rK = rsq(K);
+    m.phi = phi;
+    m.inv_phi = R(1) / phi;
+    m.c_lin = phi * P.nu * (rK * rK);
+    m.c_nl = P.forch ? R(kErgun) * rsq(phi) * rK : R(0);
+    return m;
+}
+
+template <typename R, bool PN>
+__device__ __forceinline__ Med<R> load_medium(const R* __restrict__ med, int idx, int plane,
+                                              const Phys<R>& P) {
+    if constexpr (PN) {
+        return medium_from<R>(med[idx], med[plane + idx], P);
+    } else {
+        return Med<R>{P.phi, P.inv_phi, P.c_lin, P.c_nl};
+    }
+}
+
+// Streaming, Eqs. (18) and (35), as a pull: the population i arriving at (x, y) left
+// (x - ex_i, y - ey_i) after the previous collision.  Indices wrap, which is only ever used on
+// periodic axes: on a walled axis the node is interior, so x-1 and x+1 stay in range.
+template <typename R>
+__device__ __forceinline__ void pull(const R* __restrict__ src, const Geo& G, int x, int y,
+                                     R f[9], R g[5]) {
+    const int xm = (x == 0) ? G.nx - 1 : x - 1;
+    const int xp = (x == G.nx - 1) ? 0 : x + 1;
+    const int rm = ((y == 0) ? G.ny - 1 : y - 1) * G.pitch;
+    const int rp = ((y == G.ny - 1) ? 0 : y + 1) * G.pitch;
+    const int r0 = y * G.pitch;
+    const int P = G.plane;
+    f[0] = src[0 * P + r0 + x];
+    f[1] = src[1 * P + r0 + xm];
+    f[2] = src[2 * P + rm + x];
+    f[3] = src[3 * P + r0 + xp];
+    f[4] = src[4 * P + rp + x];
+    f[5] = src[5 * P + rm + xm];
+    f[6] = src[6 * P + rm + xp];
+    f[7] = src[7 * P + rp + xp];
+    f[8] = src[8 * P + rp + xm];
+    g[0] = src[9 * P + r0 + x];
+    g[1] = src[10 * P + r0 + xm];
+    g[2] = src[11 * P + rm + x];
+    g[3] = src[12 * P + r0 + xp];
+    g[4] = src[13 * P + rp + x];
+}
+
+// Eqs. (36), (22), (21), (23), (4) at a fluid node, on deviation populations.
+template <typename R>
+__device__ __forceinline__ Mac<R> fluid_macros(const R f[9], const R g[5], const Med<R>& md,
+                                               const Phys<R>& P) {
+    Mac<R> m;
+    const R theta = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
+    const R Gx = P.ax;
+    const R Gy = P.ay + P.gbeta * theta;
+    const R jx = (f[1] - f[3]) + (f[5] - f[6]) - (f[7] - f[8]);
+    const R jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    const R hphi = R(0.5) * md.phi;
+    const R vx = jx * P.inv_rho0 + hphi * Gx;
+    const R vy = jy * P.inv_rho0 + hphi * Gy;
+    const R l0 = R(0.5) + R(0.25) * md.c_lin;
+    const R l1 = R(0.5) * md.c_nl;
+    const R vmag = sqrt(vx * vx + vy * vy);
+    const R inv_den = R(1) / (l0 + sqrt(l0 * l0 + l1 * vmag));
+    const R ux = vx * inv_den, uy = vy * inv_den;
+    const R uu = ux * ux + uy * uy;
+    const R sum18 = ((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8]));
+    // phi p = cs^2/(1 - w0) [sum_{i>=1} f_i + rho0 s0(u)], s0 = -w0 |u|^2 / (2 phi cs^2)
+    m.P = R(0.6) * (sum18 - R(2.0 / 3.0) * P.rho0 * uu * md.inv_phi);
+    const R drag = md.c_lin + md.c_nl * sqrt(uu);
+    m.theta = theta;
+    m.ux = ux;
+    m.uy = uy;
+    m.Fx = md.phi * Gx - drag * ux;
+    m.Fy = md.phi * Gy - drag * uy;
+    return m;
+}
+
+// Non-equilibrium extrapolation at a wall node whose inward neighbour x_f holds (f, g) with
+// macroscopics mf and medium mdf.  All populations are replaced by the wall equilibrium
+// (u = 0, phi_b p_b = phi_f p_f, T_b) plus the neighbour's non-equilibrium part.  Because the
+// pressure parts of the two equilibria cancel, f_b,i = f_f,i - rho0 s_i(u_f; phi_f).
+template <typename R>
+__device__ __forceinline__ void nee_wall(R f[9], R g[5], const Mac<R>& mf, const Med<R>& mdf,
+                                         R theta_b, const Phys<R>& P) {
+    const R ux = mf.ux, uy = mf.uy;
+    const R ip = mdf.inv_phi;
+    const R uu = ux * ux + uy * uy;
+    const R r0 = P.rho0;
+    // rho0 s_i(u) = rho0 w_i [3 e.u + 4.5 (e.u)^2 / phi - 1.5 |u|^2 / phi]   (Eq. (14))
+    const R base = R(1.5) * uu * ip;
+    const R c1 = r0 * R(1.0 / 9.0), c5 = r0 * R(1.0 / 36.0);
+    f[0] -= r0 * R(4.0 / 9.0) * (-base);
+    f[1] -= c1 * (R(3) * ux + R(4.5) * ux * ux * ip - base);
+    f[2] -= c1 * (R(3) * uy + R(4.5) * uy * uy * ip - base);
+    f[3] -= c1 * (R(-3) * ux + R(4.5) * ux * ux * ip - base);
+    f[4] -= c1 * (R(-3) * uy + R(4.5) * uy * uy * ip - base);
+    const R a = ux + uy, b = uy - ux;
+    f[5] -= c5 * (R(3) * a + R(4.5) * a * a * ip - base);
+    f[6] -= c5 * (R(3) * b + R(4.5) * b * b * ip - base);
+    f[7] -= c5 * (R(-3) * a + R(4.5) * a * a * ip - base);
+    f[8] -= c5 * (R(-3) * b + R(4.5) * b * b * ip - base);
+    // g_b = wt T_b + g_f - wt T_f (1 + e.u_f / (sigma csT^2))            (Eq. (37a))
+    const R dth = theta_b - mf.theta;
+    const R Tf = P.T0 + mf.theta;
+    const R k = P.wt1 * Tf * P.u_coef;
+    g[0] += P.wt0 * dth;
+    g[1] += P.wt1 * dth - k * ux;
+    g[2] += P.wt1 * dth - k * uy;
+    g[3] += P.wt1 * dth + k * ux;
+    g[4] += P.wt1 * dth + k * uy;
+}
+
+// Collision in moment space, Eq. (17) with s0 = s3 = s5 = 1 (Sec. 4) and Eq. (34) with
+// zeta0 = 1, no heat source; f, g hold post-streaming deviations on entry and post-collision
+// deviations on exit.
+template <typename R>
+__device__ __forceinline__ void collide(R f[9], R g[5], const Mac<R>& m, const Med<R>& md,
+                                        const Phys<R>& P) {
+    // m' = M f' (rows of Eq. (11)); m0', m3', m5' are not needed: s0 = s3 = s5 = 1
+    const R s14 = (f[1] + f[2]) + (f[3] + f[4]);
+    const R s58 = (f[5] + f[6]) + (f[7] + f[8]);
+    const R qx = (f[5] - f[6]) - (f[7] - f[8]);
+    const R qy = (f[5] + f[6]) - (f[7] + f[8]);
+    const R m1 = R(2) * s58 - s14 - R(4) * f[0];
+    const R m2 = s58 - R(2) * s14 + R(4) * f[0];
+    const R m4 = qx - R(2) * (f[1] - f[3]);
+    const R m6 = qy - R(2) * (f[2] - f[4]);
+    const R m7 = (f[1] - f[2]) + (f[3] - f[4]);
+    const R m8 = (f[5] - f[6]) + (f[7] - f[8]);
+    // equilibrium moments (Eq. (16) less the rest state) and forcing (Eq. (19))
+    const R r0 = P.rho0, ux = m.ux, uy = m.uy;
+    const R rip = r0 * md.inv_phi;
+    const R uu = ux * ux + uy * uy;
+    const R e_eq = R(6) * m.P + R(3) * rip * uu;
+    const R eps_eq = R(-9) * m.P - R(3) * rip * uu;
+    const R pxx_eq = rip * (ux * ux - uy * uy);
+    const R pxy_eq = rip * ux * uy;
+    const R S1 = R(6) * rip * (ux * m.Fx + uy * m.Fy);
+    const R S7 = R(2) * rip * (ux * m.Fx - uy * m.Fy);
+    const R S8 = rip * (ux * m.Fy + uy * m.Fx);
+    const R rFx = r0 * m.Fx, rFy = r0 * m.Fy;
+    // relaxation, then scaling by 1/|row|^2 for M^-1 = M^T diag(1/|row|^2)
+    const R a1 = (m1 - P.s_e * (m1 - e_eq) + P.os_e * S1) * R(1.0 / 36.0);
+    const R a2 = (m2 - P.s_eps * (m2 - eps_eq) - P.os_eps * S1) * R(1.0 / 36.0);
+    const R a3 = (r0 * ux + R(0.5) * rFx) * R(1.0 / 6.0);
+    const R a4 = (m4 - P.s_q * (m4 + r0 * ux) - P.os_q * rFx) * R(1.0 / 12.0);
+    const R a5 = (r0 * uy + R(0.5) * rFy) * R(1.0 / 6.0);
+    const R a6 = (m6 - P.s_q * (m6 + r0 * uy) - P.os_q * rFy) * R(1.0 / 12.0);
+    const R a7 = (m7 - P.s_v * (m7 - pxx_eq) + P.os_v * S7) * R(0.25);
+    const R a8 = (m8 - P.s_v * (m8 - pxy_eq) + P.os_v * S8) * R(0.25);
+    // f' = M^T a (columns of Eq. (11)); a0 = 0 because the post-collision m0' is 0
+    const R c14 = -a1 - R(2) * a2;
+    const R c58 = R(2) * a1 + a2;
+    f[0] = R(4) * (a2 - a1);
+    f[1] = c14 + (a3 - R(2) * a4) + a7;
+    f[2] = c14 + (a5 - R(2) * a6) - a7;
+    f[3] = c14 - (a3 - R(2) * a4) + a7;
+    f[4] = c14 - (a5 - R(2) * a6) - a7;
+    const R px = a3 + a4, py = a5 + a6;
+    f[5] = c58 + px + py + a8;
+    f[6] = c58 - px + py - a8;
+    f[7] = c58 - px - py + a8;
+    f[8] = c58 + px - py - a8;
+
+    // thermal: n' = N g' (rows of Eq. (28)); n0' = theta is conserved (zeta0 = 1)
+    const R T = P.T0 + m.theta;
+    const R n1 = g[1] - g[3];
+    const R n2 = g[2] - g[4];
+    const R n3 = (g[1] + g[2]) + (g[3] + g[4]) - R(4) * g[0];
+    const R n4 = (g[1] - g[2]) + (g[3] - g[4]);
+    const R b0 = m.theta * R(0.2);
+    const R b1 = (n1 - P.z_T * (n1 - ux * T * P.inv_sigma)) * R(0.5);
+    const R b2 = (n2 - P.z_T * (n2 - uy * T * P.inv_sigma)) * R(0.5);
+    const R b3 = (n3 - P.z3 * (n3 - P.varpi * m.theta)) * R(0.05);
+    const R b4 = (n4 - P.z4 * n4) * R(0.25);
+    // g' = N^T b (columns of Eq. (28))
+    g[0] = b0 - R(4) * b3;
+    g[1] = (b0 + b3) + (b1 + b4);
+    g[2] = (b0 + b3) + (b2 - b4);
+    g[3] = (b0 + b3) - (b1 - b4);
+    g[4] = (b0 + b3) - (b2 + b4);
+}
+
+// Wall temperature rule: an isothermal side fixes T; at a corner of two isothermal sides the
+// mean is used; on adiabatic sides T_b = T_f (zero normal gradient).
+template <typename R>
+__device__ __forceinline__ R wall_theta(bool onW, bool onE, bool onS, bool onN, R theta_f,
+                                        const Phys<R>& P) {
+    const int sx = onW ? 0 : (onE ? 1 : -1);
+    const int sy = onS ? 2 : (onN ? 3 : -1);
+    const bool isoX = sx >= 0 && P.iso[sx];
+    const bool isoY = sy >= 0 && P.iso[sy];
+    if (isoX && isoY) return R(0.5) * (P.theta_wall[sx] + P.theta_wall[sy]);
+    if (isoX) return P.theta_wall[sx];
+    if (isoY) return P.theta_wall[sy];
+    return theta_f;
+}
+
+// Post-streaming, post-wall-reconstruction state of node (x, y): populations, macroscopics and
+// medium.  Wall nodes gather around their inward neighbour (the diagonal one at corners).
+template <typename R, bool PN>
+__device__ __forceinline__ void node_state(const R* __restrict__ src, const R* __restrict__ med,
+                                           const Geo& G, const Phys<R>& P, int x, int y, R f[9],
+                                           R g[5], Mac<R>& m, Med<R>& md) {
+    const bool onW = G.wallW && x == 0;
+    const bool onE = G.wallE && x == G.nx - 1;
+    const bool onS = G.wallS && y == 0;
+    const bool onN = G.wallN && y == G.ny - 1;
+    if (!(onW || onE || onS || onN)) {
+        pull<R>(src, G, x, y, f, g);
+        md = load_medium<R, PN>(med, y * G.pitch + x, G.plane, P);
+        m = fluid_macros<R>(f, g, md, P);
+        return;
+    }
+    const int xf = x + (onW ? 1 : 0) - (onE ? 1 : 0);
+    const int yf = y + (onS ? 1 : 0) - (onN ? 1 : 0);
+    pull<R>(src, G, xf, yf, f, g);
+    const Med<R> mdf = load_medium<R, PN>(med, yf * G.pitch + xf, G.plane, P);
+    const Mac<R> mf = fluid_macros<R>(f, g, mdf, P);
+    const R theta_b = wall_theta<R>(onW, onE, onS, onN, mf.theta, P);
+    nee_wall<R>(f, g, mf, mdf, theta_b, P);
+    md = load_medium<R, PN>(med, y * G.pitch + x, G.plane, P);
+    m.theta = theta_b;
+    m.ux = R(0);
+    m.uy = R(0);
+    m.P = mf.P;
+    m.Fx = md.phi * P.ax;
+    m.Fy = md.phi * (P.ay + P.gbeta * theta_b);
+}
+
+// Work-group id -> tile id such that each XCD (work-groups are dealt to the 8 XCDs round
+// robin) gets one contiguous run of tiles; neighbouring tiles then share an L2.
+__device__ __forceinline__ int xcd_tile(int wg, int nwg) {
+    const int q = nwg >> 3, r = nwg & 7;
+    const int xcd = wg & 7, k = wg >> 3;
+    return (xcd < r) ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
+}
+
+}  // namespace lbm

@@ -1,0 +1,60 @@
+// lbm_internal.hpp -- launchers shared between the ABI (lbm_abi.cpp) and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lbm_device.hpp"
+
+namespace lbm {
+
+constexpr int kTileX = 256;      // nodes (work-items) per work-group of the step kernel
+constexpr int kObserveWG = 512;  // work-groups of the observables pass
+constexpr int kPitchAlign = 64;  // row pitch in elements
+
+template <typename R>
+hipError_t launch_step(const void* src, void* dst, const void* med, const Geo& G,
+                       const Phys<R>& P, hipStream_t s);
+template <typename R>
+hipError_t launch_observe(const void* src, const void* med, const Geo& G, const Phys<R>& P,
+                          void* ux, void* uy, void* p, void* T, double* part, int nparts,
+                          double L_over_dT, double* out, hipStream_t s);
+template <typename R>
+hipError_t launch_rest(void* dst, const Geo& G, double g0, double g1, hipStream_t s);
+template <typename R>
+hipError_t launch_pitch_copy(void* dst, const void* src, const Geo& G, double v, hipStream_t s);
+
+// Adjoint (lbm_adjoint.hip)
+template <typename R>
+hipError_t launch_adjoint_seed(const void* state, void* lam, const Geo& G, const Phys<R>& P,
+                               double L_over_dT, hipStream_t s);
+template <typename R>
+hipError_t launch_adjoint_step(const void* state, const void* lam_in, void* lam_out,
+                               const void* med, double* gphi, double* gK, const Geo& G,
+                               const Phys<R>& P, hipStream_t s);
+template <typename R>
+hipError_t launch_fill(void* dst, size_t n, hipStream_t s);
+hipError_t launch_fill_f64(double* dst, size_t n, hipStream_t s);
+hipError_t launch_unpitch_scale(double* dst, const double* src, const Geo& G, double scale,
+                                hipStream_t s);
+
+// Batched form (lbm_batch.hip)
+struct BatchCavity {
+    Geo G;
+    long long off;     // element offset of the cavity's state inside a state buffer
+    int tile0;         // first tile id of the cavity
+    int tiles_x;       // tiles per row
+};
+
+template <typename R>
+struct BatchTable {
+    const BatchCavity* cav;  // device array [n]
+    const Phys<R>* phys;     // device array [n]
+    int ncav;
+    int ntiles;
+};
+
+template <typename R>
+hipError_t launch_batch_step(const void* src, void* dst, const BatchTable<R>& T, int nodes_x,
+                             int wg_size, int nwg, hipStream_t s);
+
+}  // namespace lbm

@@ -1,0 +1,260 @@
+// lbm_kernels.hip -- plain (single cavity) kernels: the fused time step, the observables
+// pass, the wall Nusselt reduction and state initialisation.
+#include "lbm_device.hpp"
+#include "lbm_internal.hpp"
+
+namespace lbm {
+
+// One time step for every node: pull (Eqs. (18), (35)) -> wall reconstruction -> macroscopic
+// recovery (Eqs. (36), (22), (21), (23), (4)) -> collision (Eqs. (17), (34)) -> store.
+// One work-item per node; a work-group covers kTileX consecutive nodes of one row.
+template <typename R, bool PN>
+__global__ __launch_bounds__(kTileX) void step_kernel(const R* __restrict__ src,
+                                                      R* __restrict__ dst,
+                                                      const R* __restrict__ med, Geo G,
+                                                      Phys<R> P, int tiles_x) {
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int y = t / tiles_x;
+    const int x = (t - y * tiles_x) * kTileX + threadIdx.x;
+    if (x >= G.nx) return;
+    R f[9], g[5];
+    Mac<R> m;
+    Med<R> md;
+    node_state<R, PN>(src, med, G, P, x, y, f, g, m, md);
+    collide<R>(f, g, m, md, P);
+    const int o = y * G.pitch + x;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(f[i], dst + i * G.plane + o);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) __builtin_nontemporal_store(g[i], dst + (9 + i) * G.plane + o);
+}
+
+// Wave-level reductions over the 64 lanes of a wavefront.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    return v;
+}
+
+// Macroscopic fields at the current time level, plus per-work-group partial results:
+// part[3 * b + 0] = max |u|, part[3 * b + 1] = sum of stored f' (mass deviation),
+// part[3 * b + 2] = 1 if a field is not finite.  Grid-stride over nodes.
+template <typename R, bool PN>
+__global__ __launch_bounds__(256) void observe_kernel(const R* __restrict__ src,
+                                                      const R* __restrict__ med, Geo G,
+                                                      Phys<R> P, R* __restrict__ ux_out,
+                                                      R* __restrict__ uy_out,
+                                                      R* __restrict__ p_out,
+                                                      R* __restrict__ T_out,
+                                                      double* __restrict__ part) {
+    const int n = G.nx * G.ny;
+    double umax = 0.0, mass = 0.0, bad = 0.0;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+        const int y = k / G.nx, x = k - y * G.nx;
+        R f[9], g[5];
+        Mac<R> m;
+        Med<R> md;
+        node_state<R, PN>(src, med, G, P, x, y, f, g, m, md);
+        const R p = (m.P + P.rho0 * R(1.0 / 3.0)) * md.inv_phi;
+        const R T = P.T0 + m.theta;
+        if (ux_out) ux_out[k] = m.ux;
+        if (uy_out) uy_out[k] = m.uy;
+        if (p_out) p_out[k] = p;
+        if (T_out) T_out[k] = T;
+        const double sp = sqrt(double(m.ux) * double(m.ux) + double(m.uy) * double(m.uy));
+        umax = fmax(umax, sp);
+        if (!isfinite(sp) || !isfinite(double(p)) || !isfinite(double(T))) bad = 1.0;
+        const int o = y * G.pitch + x;
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) s += double(src[i * G.plane + o]);
+        mass += s;
+    }
+    __shared__ double red[3][4];
+    umax = wave_max(umax);
+    mass = wave_sum(mass);
+    bad = wave_max(bad);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][w] = umax;
+        red[1][w] = mass;
+        red[2][w] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = red[0][0], b = red[1][0], c = red[2][0];
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
+            a = fmax(a, red[0][i]);
+            b += red[1][i];
+            c = fmax(c, red[2][i]);
+        }
+        part[3 * blockIdx.x + 0] = a;
+        part[3 * blockIdx.x + 1] = b;
+        part[3 * blockIdx.x + 2] = c;
+    }
+}
+
+// Temperature deviation theta = T - T0 at (x, y) after streaming and wall reconstruction.
+template <typename R>
+__device__ __forceinline__ double node_theta(const R* __restrict__ src, const Geo& G,
+                                             const Phys<R>& P, int x, int y) {
+    const bool onW = G.wallW && x == 0;
+    const bool onE = G.wallE && x == G.nx - 1;
+    const bool onS = G.wallS && y == 0;
+    const bool onN = G.wallN && y == G.ny - 1;
+    const int xf = x + (onW ? 1 : 0) - (onE ? 1 : 0);
+    const int yf = y + (onS ? 1 : 0) - (onN ? 1 : 0);
+    R f[9], g[5];
+    pull<R>(src, G, xf, yf, f, g);
+    const R th = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
+    if (!(onW || onE || onS || onN)) return double(th);
+    return double(wall_theta<R>(onW, onE, onS, onN, th, P));
+}
+
+// Eq. (38): Nu(y) = -L dT/dx / dT at the west (hot) and east (cold) walls with the
+// fourth-order one-sided five-point derivative, averaged by the trapezoid rule over the
+// ny wall nodes; part[0..2] = partial results of observe_kernel (nparts work-groups).
+// One work-group; writes out[0] nu_hot, out[1] nu_cold, out[2] max |u|, out[3] sum f',
+// out[4] non-finite flag.
+template <typename R>
+__global__ __launch_bounds__(256) void nusselt_kernel(const R* __restrict__ src, Geo G,
+                                                      Phys<R> P, double L_over_dT,
+                                                      const double* __restrict__ part,
+                                                      int nparts, double* __restrict__ out) {
+    double h = 0.0, c = 0.0;
+    if (G.nx >= 5) {
+        for (int y = threadIdx.x; y < G.ny; y += blockDim.x) {
+            double Th[5], Tc[5];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                Th[k] = node_theta<R>(src, G, P, k, y);
+                Tc[k] = node_theta<R>(src, G, P, G.nx - 1 - k, y);
+            }
+            const double dh = (-25.0 * Th[0] + 48.0 * Th[1] - 36.0 * Th[2] + 16.0 * Th[3] -
+                               3.0 * Th[4]) / 12.0;
+            const double dc = (25.0 * Tc[0] - 48.0 * Tc[1] + 36.0 * Tc[2] - 16.0 * Tc[3] +
+                               3.0 * Tc[4]) / 12.0;
+            const double w = (y == 0 || y == G.ny - 1) ? 0.5 : 1.0;
+            h += w * dh;
+            c += w * dc;
+        }
+    }
+    __shared__ double red[2][4];
+    h = wave_sum(h);
+    c = wave_sum(c);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wv] = h;
+        red[1][wv] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sh = 0.0, sc = 0.0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+            sh += red[0][i];
+            sc += red[1][i];
+        }
+        const double scale = -L_over_dT / double(G.ny - 1);
+        out[0] = scale * sh;
+        out[1] = scale * sc;
+        double a = 0.0, b = 0.0, f = 0.0;
+        for (int i = 0; i < nparts; ++i) {
+            a = fmax(a, part[3 * i + 0]);
+            b += part[3 * i + 1];
+            f = fmax(f, part[3 * i + 2]);
+        }
+        out[2] = a;
+        out[3] = b;
+        out[4] = f;
+    }
+}
+
+// Rest state (u = 0, phi p = rho0 cs^2, T = T_init) as deviations: f' = 0, g' = wt (T_init - T0).
+template <typename R>
+__global__ void rest_kernel(R* __restrict__ dst, Geo G, R g0, R g1) {
+    const int n = G.plane;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) dst[i * n + k] = R(0);
+        dst[9 * n + k] = g0;
+#pragma unroll
+        for (int i = 1; i < 5; ++i) dst[(9 + i) * n + k] = g1;
+    }
+}
+
+// Pitched copy of a dense [ny][nx] field into a [ny][pitch] plane; a NULL source fills v.
+template <typename R>
+__global__ void pitch_copy_kernel(R* __restrict__ dst, const R* __restrict__ src, Geo G, R v) {
+    const int n = G.nx * G.ny;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+        const int y = k / G.nx, x = k - y * G.nx;
+        dst[y * G.pitch + x] = src ? src[k] : v;
+    }
+}
+
+// ---- launchers --------------------------------------------------------------------------------
+
+template <typename R>
+hipError_t launch_step(const void* src, void* dst, const void* med, const Geo& G,
+                       const Phys<R>& P, hipStream_t s) {
+    const int tiles_x = (G.nx + kTileX - 1) / kTileX;
+    const int nwg = tiles_x * G.ny;
+    if (med)
+        step_kernel<R, true><<<nwg, kTileX, 0, s>>>((const R*)src, (R*)dst, (const R*)med, G, P,
+                                                    tiles_x);
+    else
+        step_kernel<R, false><<<nwg, kTileX, 0, s>>>((const R*)src, (R*)dst, nullptr, G, P,
+                                                     tiles_x);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_observe(const void* src, const void* med, const Geo& G, const Phys<R>& P,
+                          void* ux, void* uy, void* p, void* T, double* part, int nparts,
+                          double L_over_dT, double* out, hipStream_t s) {
+    if (med)
+        observe_kernel<R, true><<<nparts, 256, 0, s>>>((const R*)src, (const R*)med, G, P,
+                                                       (R*)ux, (R*)uy, (R*)p, (R*)T, part);
+    else
+        observe_kernel<R, false><<<nparts, 256, 0, s>>>((const R*)src, nullptr, G, P, (R*)ux,
+                                                        (R*)uy, (R*)p, (R*)T, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    nusselt_kernel<R><<<1, 256, 0, s>>>((const R*)src, G, P, L_over_dT, part, nparts, out);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_rest(void* dst, const Geo& G, double g0, double g1, hipStream_t s) {
+    rest_kernel<R><<<1024, 256, 0, s>>>((R*)dst, G, R(g0), R(g1));
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_pitch_copy(void* dst, const void* src, const Geo& G, double v, hipStream_t s) {
+    pitch_copy_kernel<R><<<1024, 256, 0, s>>>((R*)dst, (const R*)src, G, R(v));
+    return hipGetLastError();
+}
+
+template hipError_t launch_step<float>(const void*, void*, const void*, const Geo&,
+                                       const Phys<float>&, hipStream_t);
+template hipError_t launch_step<double>(const void*, void*, const void*, const Geo&,
+                                        const Phys<double>&, hipStream_t);
+template hipError_t launch_observe<float>(const void*, const void*, const Geo&,
+                                          const Phys<float>&, void*, void*, void*, void*,
+                                          double*, int, double, double*, hipStream_t);
+template hipError_t launch_observe<double>(const void*, const void*, const Geo&,
+                                           const Phys<double>&, void*, void*, void*, void*,
+                                           double*, int, double, double*, hipStream_t);
+template hipError_t launch_rest<float>(void*, const Geo&, double, double, hipStream_t);
+template hipError_t launch_rest<double>(void*, const Geo&, double, double, hipStream_t);
+template hipError_t launch_pitch_copy<float>(void*, const void*, const Geo&, double, hipStream_t);
+template hipError_t launch_pitch_copy<double>(void*, const void*, const Geo&, double,
+                                              hipStream_t);
+
+}  // namespace lbm

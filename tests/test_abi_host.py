@@ -1,0 +1,129 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every symbol the
+header declares, derives the paper's parameters like the oracle does, and rejects bad arguments
+before any device call."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import paper_1308_2071_amd as m
+    m.library()
+    return m
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(lbm):
+    from paper_1308_2071_amd import _abi
+    names = header_functions()
+    assert len(names) >= 18
+    lib = C.CDLL(_abi.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_abi.EXPORTED)
+
+
+def test_param_struct_layout_matches_header(lbm):
+    # the ctypes mirror must have the C layout: 8-byte aligned doubles after int32 pairs
+    from paper_1308_2071_amd._abi import LbmObs, LbmParams
+    assert C.sizeof(LbmParams) == 8 + 16 + 32 + 4 * 8 + 4 * 8 + 5 * 8 + 8 + 8 + 16 + 3 * 8 + 8
+    assert C.sizeof(LbmObs) == 48
+
+
+def test_defaults_are_the_papers(lbm):
+    p = lbm.lbm_default_params()
+    assert (p.rho0, p.varpi, p.J, p.sigma, p.Ma) == (1.0, -2.0, 1.0, 1.0, 0.1)
+    assert (p.s_e, p.s_eps, p.s_q, p.zeta3, p.zeta4) == (1.1, 1.1, 1.2, 1.5, 1.5)
+    assert tuple(p.bc) == (0, 0, 1, 1)
+    assert tuple(p.T_wall)[:2] == (1.0, 0.0)
+
+
+@pytest.mark.parametrize("case", [
+    dict(nx=64, ny=64, Ra=1e3, Pr=1.0, Da=1e-2),
+    dict(nx=256, ny=256, Ra=1e5, Pr=1.0, Da=1e-2),
+    dict(nx=4096, ny=4096, Ra=1e6, Pr=0.71, Da=1e-3),
+    dict(nx=100, ny=37, Ra=3e4, Pr=7.0, Da=-1.0, J=1.3, sigma=0.8, varpi=-1.0),
+])
+def test_derived_parameters_match_oracle(lbm, oracle, case):
+    d = lbm.lbm_derived(lbm.make_params(**case))
+    r = oracle.derived(**case)
+    for k in ("L", "tau_v", "tau_T", "nu_e", "nu", "gbeta", "dT", "T0"):
+        assert d[k] == pytest.approx(r[k], rel=1e-14), k
+    assert d["K"] == pytest.approx(r["K_uniform"], rel=1e-14) or (np.isinf(d["K"]) and
+                                                                   np.isinf(r["K_uniform"]))
+
+
+def status_of(lbm, **kw):
+    from paper_1308_2071_amd import _abi
+    p = lbm.make_params(**kw)
+    n = C.c_size_t()
+    return _abi.library().lbm_workspace_size(C.byref(p), 100, C.byref(n))
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=4),                                  # five-point stencil needs 5 nodes
+    dict(ny=3),
+    dict(bc=(2, 0, 1, 1)),                       # unpaired periodic side
+    dict(bc=(0, 0, 2, 1)),
+    dict(bc=(0, 0, 1, 7)),                       # unknown side condition
+    dict(varpi=1.0),                             # Eq. (29): varpi < 1
+    dict(rho0=0.0),
+    dict(sigma=-1.0),
+    dict(tau_v=0.5),                             # tau must exceed 1/2
+    dict(tau_T=0.4),
+    dict(Ra=-1.0),
+    dict(dtype=5),
+    dict(s_q=2.5),
+    dict(checkpoint_every=-3),
+    dict(nx=40000, ny=40000),                    # beyond the 2^31-element state limit
+])
+def test_invalid_parameters_are_rejected(lbm, bad):
+    assert status_of(lbm, **bad) == -1  # LBM_E_INVAL
+    assert lbm.lbm_last_error() != ""
+
+
+def test_init_rejects_before_any_device_call(lbm):
+    from paper_1308_2071_amd import _abi
+    L = _abi.library()
+    p = lbm.make_params(nx=16, ny=16)
+    h = C.c_void_p()
+    # null workspace
+    assert L.lbm_init(C.byref(h), C.byref(p), None, None, 0.5, None, 1 << 20, None) == -1
+    # phi_uniform outside (0, 1]
+    assert L.lbm_init(C.byref(h), C.byref(p), None, None, 1.5, 256, 1 << 20, None) == -1
+    # misaligned workspace
+    assert L.lbm_init(C.byref(h), C.byref(p), None, None, 0.5, 8, 1 << 20, None) == -1
+    # too small workspace (no device call either)
+    assert L.lbm_init(C.byref(h), C.byref(p), None, None, 0.5, 256, 64, None) == -2
+    assert h.value is None
+
+
+def test_null_context_and_status_strings(lbm):
+    from paper_1308_2071_amd import _abi
+    L = _abi.library()
+    assert L.lbm_step(None, 1) == -1
+    assert L.lbm_grad(None, 1.0, None, None) == -1
+    assert L.lbm_destroy(None) == 0
+    for s, name in [(0, "LBM_OK"), (-1, "LBM_E_INVAL"), (-4, "LBM_E_DIVERGED"),
+                    (-6, "LBM_E_UNSUPPORTED"), (17, "LBM_E_UNKNOWN")]:
+        assert lbm.lbm_status_string(s) == name
+
+
+def test_workspace_grows_with_tape(lbm):
+    base = lbm.lbm_workspace_size(lbm.make_params(nx=64, ny=64), 0)
+    tape = lbm.lbm_workspace_size(lbm.make_params(nx=64, ny=64, checkpoint_every=100), 2000)
+    state = 14 * 64 * 64 * 4
+    assert base >= 2 * state
+    # 20 checkpoints + 100 segment states + 2 adjoint buffers
+    assert tape - base >= (20 + 100 + 2) * state

@@ -1,0 +1,158 @@
+"""Parity of the HIP time step with the FP64 CPU oracle, element by element on the same seeded
+inputs: u_x, u_y, p, T at every node and the two wall Nusselt numbers (Eq. (38)).
+
+Tolerances: FP64 max-abs 1e-12 after short runs on tiny grids and 1e-10 after the 20k steps of
+the 64 x 64 cavity; FP32 1e-4 of each field's range (range = max - min of the oracle's field)
+and Nu within 1e-3.  In the first steps a field's range can be far below its magnitude (p is
+~0.8 everywhere while its range is ~1e-4), where an FP32 output cannot even represent it to 1e-4
+of the range; there the range is floored at 1e-2 of the field's magnitude, so the bar never
+drops below ~15 FP32 ulps of the value.  For FP32 runs the oracle receives the FP32-rounded phi
+and K, so only the arithmetic differs.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ref
+from paper_1308_2071_amd import Cavity, workloads
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("ux", "uy", "p", "T")
+
+
+def run_pair(params, steps, phi=None, K=None, phi_u=0.6, dtype="fp64", chunks=None):
+    """Run the same cavity on the GPU and in the oracle; yields (gpu_obs, ref_obs) at each
+    chunk boundary."""
+    if dtype == "fp32":
+        phi = None if phi is None else phi.astype(np.float32).astype(np.float64)
+        K = None if K is None else K.astype(np.float32).astype(np.float64)
+        phi_u = float(np.float32(phi_u))
+    tdt = torch.float64
+    cav = Cavity(dict(params, dtype=dtype),
+                 phi=None if phi is None else torch.tensor(phi, dtype=tdt),
+                 K=None if K is None else torch.tensor(K, dtype=tdt), phi_uniform=phi_u)
+    lat = ref.RefLattice(phi=phi, K=K, phi_uniform=phi_u, **params)
+    chunks = chunks or [steps]
+    for n in chunks:
+        cav.step(n)
+        lat.step(n)
+        g = cav.observables()
+        r = lat.observables()
+        yield {k: (g[k].double().cpu().numpy() if k in FIELDS else g[k]) for k in g}, r
+    cav.close()
+
+
+def assert_match(g, r, dtype, atol64=1e-12, what="", floor=1e-2):
+    for k in FIELDS:
+        a, b = g[k], r[k]
+        if dtype == "fp64":
+            err = np.abs(a - b).max()
+            assert err <= atol64, f"{what} {k}: max-abs {err:.3e} > {atol64:.1e}"
+        else:
+            rng = max(b.max() - b.min(), floor * np.abs(b).max(), 1e-12)
+            err = np.abs(a - b).max() / rng
+            assert err <= 1e-4, f"{what} {k}: {err:.3e} of range"
+    tol = atol64 * 100 if dtype == "fp64" else 1e-3
+    assert abs(g["nu_hot"] - r["nu_hot"]) <= tol, (what, g["nu_hot"], r["nu_hot"])
+    assert abs(g["nu_cold"] - r["nu_cold"]) <= tol, (what, g["nu_cold"], r["nu_cold"])
+    assert not g["diverged"]
+
+
+ISO, ADIA, PER = 0, 1, 2
+BC_CASES = {
+    "side_heated": dict(bc=(ISO, ISO, ADIA, ADIA), T_wall=(1.0, 0.0, 0.0, 0.0)),
+    "mixed": dict(bc=(ADIA, ISO, ISO, ADIA), T_wall=(0.0, 0.2, 1.0, 0.0)),
+    "all_iso": dict(bc=(ISO, ISO, ISO, ISO), T_wall=(1.0, 0.0, 0.7, 0.1)),
+    "all_adia": dict(bc=(ADIA, ADIA, ADIA, ADIA), T_wall=(0.0, 0.0, 0.0, 0.0), T_init=0.3),
+    "channel_x": dict(bc=(PER, PER, ISO, ADIA), T_wall=(0.0, 0.0, 1.0, 0.0),
+                      ext_accel=(1e-5, 0.0)),
+    "channel_y": dict(bc=(ISO, ISO, PER, PER), T_wall=(1.0, 0.0, 0.0, 0.0),
+                      ext_accel=(0.0, 2e-5)),
+    "periodic": dict(bc=(PER, PER, PER, PER), ext_accel=(3e-5, -1e-5), T_init=0.5),
+}
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", [(5, 5), (7, 6), (16, 16), (300, 70)])
+@pytest.mark.parametrize("bcname", list(BC_CASES))
+def test_tiny_grids_step_by_step(shape, bcname, dtype):
+    nx, ny = shape
+    params = dict(nx=nx, ny=ny, Ra=1e5, Pr=0.71, **BC_CASES[bcname])
+    if bcname in ("channel_x", "periodic"):
+        params["tau_v"] = 0.8 if bcname == "channel_x" else 0.7
+    if bcname.startswith("channel") or bcname == "periodic":
+        params["tau_T"] = 0.9
+        params["gbeta"] = 1e-3
+    phi, K = workloads.random_medium(ny, nx, seed=nx * 1000 + ny)
+    for i, (g, r) in enumerate(run_pair(params, 0, phi=phi, K=K, dtype=dtype,
+                                        chunks=[1, 1, 3, 20, 75])):
+        assert_match(g, r, dtype, what=f"{bcname} {shape} chunk {i}")
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+@pytest.mark.parametrize("forch", [0, 1])
+def test_uniform_medium_and_forchheimer_flag(dtype, forch):
+    params = dict(nx=33, ny=29, Ra=1e4, Pr=1.0, Da=3e-3, forchheimer=forch)
+    for g, r in run_pair(params, 0, phi_u=0.45, dtype=dtype, chunks=[1, 49, 150]):
+        assert_match(g, r, dtype, what=f"uniform forch={forch}")
+
+
+def test_infinite_permeability():
+    params = dict(nx=24, ny=24, Ra=1e4, Pr=0.71, Da=-1.0)   # K = infinity: no drag
+    for g, r in run_pair(params, 0, phi_u=0.9999, dtype="fp64", chunks=[10, 90]):
+        assert_match(g, r, "fp64", what="K=inf")
+
+
+def test_porous64_full_run_fp64():
+    """The 64 x 64 porous cavity (phi = 0.6, Da = 1e-2, Ra = 1e3, Pr = 1), all 20k steps."""
+    w = workloads.porous64()
+    for g, r in run_pair(w["params"], 0, phi_u=w["phi"], dtype="fp64",
+                         chunks=[1000, 19000]):
+        assert_match(g, r, "fp64", atol64=1e-10, what="porous64")
+    assert abs(r["nu_hot"] - 1.012) < 0.01  # Table 2, phi = 0.6, Ra = 1e3 (context)
+
+
+def test_graph_replay_equals_eager_launches():
+    """lbm_step replays a captured HIP graph for long runs; the result must be bitwise the
+    same as the same number of single launches."""
+    params = dict(nx=70, ny=40, Ra=1e5, Pr=0.71)
+    phi, K = workloads.random_medium(40, 70, seed=3)
+    a = Cavity(dict(params, dtype="fp32"), phi=torch.tensor(phi), K=torch.tensor(K))
+    b = Cavity(dict(params, dtype="fp32"), phi=torch.tensor(phi), K=torch.tensor(K))
+    a.step(300)           # graph chunks + remainder
+    for _ in range(300):  # one launch per call
+        b.step(1)
+    sa, sb = a.save(), b.save()
+    assert np.array_equal(sa, sb)
+
+
+def test_save_load_resume_is_bitwise():
+    params = dict(nx=50, ny=45, Ra=1e5, Pr=1.0, dtype="fp64")
+    a = Cavity(params, phi_uniform=0.5)
+    b = Cavity(params, phi_uniform=0.5)
+    a.step(137)
+    snap = a.save()
+    a.step(63)
+    b.load(snap)
+    b.step(63)
+    assert b.observables(False)["step"] == 200
+    assert np.array_equal(a.save(), b.save())
+
+
+def test_divergence_is_reported():
+    """A non-finite value in the state (here planted through lbm_load, the way a corrupted
+    checkpoint would arrive) spreads within a few steps; the library reports LBM_E_DIVERGED
+    with the flag set instead of returning garbage silently."""
+    params = dict(nx=16, ny=16, Ra=1e5, Pr=1.0, dtype="fp32")
+    cav = Cavity(params, phi_uniform=0.5)
+    cav.step(10)
+    assert not cav.observables(False)["diverged"]
+    snap = cav.save()
+    pitch = 64
+    off = 64 + (5 * pitch + 5) * 4          # plane f0, node (5, 5), after the 64-byte header
+    snap[off:off + 4] = np.frombuffer(np.float32(np.nan).tobytes(), dtype=np.uint8)
+    cav.load(snap)
+    cav.step(3)
+    o = cav.observables(fields=False)
+    assert o["diverged"] and o["status"] == -4
