@@ -82,6 +82,103 @@ def cpu_baseline(w, budget_s=15.0):
                       f"(after 1 untimed step), {dt:.1f} s"}
 
 
+def leg_batched(torch, steps=1000):
+    """64 uneven cavities in one launch per step (graph-replayed, autotuned), against the same
+    cavities stepped by the plain path: 64 launches per step, and each cavity's own graph."""
+    import tempfile
+    from paper_1308_2071_amd import Batch, Cavity, workloads
+    cav = workloads.batch64()
+    params = [dict(c["params"], dtype="fp32") for c in cav]
+    phis = [c["phi"] for c in cav]
+    nodes = sum(p["nx"] * p["ny"] for p in params)
+    with tempfile.TemporaryDirectory() as td:
+        b = Batch(params, phis, tune_cache_path=os.path.join(td, "tune.txt"))
+        shape = b.shape()
+        b.step(64)
+        secs = timed_steps(b, steps, torch)
+        s, obs = b.observables()
+        b.close()
+    mlups = nodes * steps / secs / 1e6
+    plains = [Cavity(p, phi_uniform=f) for p, f in zip(params, phis)]
+    k = 64
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(k):
+        for c in plains:
+            c.step(1)
+    torch.cuda.synchronize()
+    seq = nodes * k / (time.perf_counter() - t0) / 1e6
+    t0 = time.perf_counter()
+    for c in plains:
+        c.step(steps)
+    torch.cuda.synchronize()
+    own = nodes * steps / (time.perf_counter() - t0) / 1e6
+    for c in plains:
+        c.close()
+    return {"workload": "64 cavities, sides 64..512, Ra 1e3..1e6, Da 1e-4..1e-1, FP32",
+            "nodes": nodes, "steps": steps, "value": round(mlups, 1), "unit": "MLUPS",
+            "ms_per_step": round(secs / steps * 1e3, 5),
+            "hbm_pct": round(100 * mlups * 1e6 * BYTES_PER_NODE_FP32_UNIFORM / 1e9 / HBM_PEAK_GBS,
+                             2),
+            "bytes_per_node": BYTES_PER_NODE_FP32_UNIFORM,
+            "shape": {"nodes_per_item": shape[0], "wg": shape[1], "wgs": shape[2],
+                      "graph_steps": shape[3]},
+            "plain_64_launches_per_step_mlups": round(seq, 1),
+            "plain_per_cavity_graph_mlups": round(own, 1),
+            "speedup_vs_64_launches": round(mlups / seq, 2),
+            "speedup_vs_per_cavity_graphs": round(mlups / own, 2),
+            "diverged": any(o["diverged"] for o in obs)}
+
+
+def leg_adjoint(torch):
+    """dJ/dphi, dJ/dK of J = Nu_hot after 2000 FP32 steps of the smoothed-porosity 256^2 cavity
+    (checkpoint every 100): forward with checkpoints + backward, against 2000 plain steps."""
+    from paper_1308_2071_amd import Cavity, workloads
+    w = workloads.adjoint256()
+    n, steps, C = w["params"]["nx"], w["steps"], w["checkpoint"]
+    phi = torch.tensor(w["phi"], dtype=torch.float32)
+    K = torch.tensor(w["K"], dtype=torch.float32)
+    plain = Cavity(dict(w["params"], dtype="fp32"), phi=phi, K=K)
+    plain.step(100)
+    t_plain = timed_steps(plain, steps, torch)
+    plain.close()
+    cav = Cavity(dict(w["params"], dtype="fp32", checkpoint_every=C), phi=phi, K=K,
+                 nsteps_max=steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cav.step(steps)
+    J = cav.observables(fields=False)["nu_hot"]
+    t1 = time.perf_counter()
+    gphi, gK = cav.grad()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    cav.close()
+    return {"workload": "256x256 smoothed porosity, Ra 1e5, Pr 1, FP32, 2000 steps, "
+                        "checkpoint every 100",
+            "J_nu_hot": J, "forward_s": round(t1 - t0, 4), "backward_s": round(t2 - t1, 4),
+            "plain_2000_steps_s": round(t_plain, 4),
+            "total_vs_plain": round((t2 - t0) / t_plain, 2),
+            "backward_mlups": round(n * n * steps / (t2 - t1) / 1e6, 1),
+            "grad_max_abs_phi": float(gphi.abs().max()), "grad_max_abs_K": float(gK.abs().max())}
+
+
+def leg_porous256(torch, steps=2000):
+    """The 256^2 cavity (phi = 0.4, Da = 1e-2, Ra = 1e5, Pr = 1) in FP32 and FP64; its state is
+    cache-resident (3.7 / 7.3 MB per buffer), so its bandwidth is 'effective'."""
+    from paper_1308_2071_amd import Cavity, workloads
+    w = workloads.porous256()
+    out = {"workload": "256x256, phi 0.4, Da 1e-2, Ra 1e5, Pr 1", "steps": steps}
+    for dt, bpn in (("fp32", BYTES_PER_NODE_FP32_UNIFORM), ("fp64", BYTES_PER_NODE_FP64_UNIFORM)):
+        c = Cavity(dict(w["params"], dtype=dt), phi_uniform=w["phi"])
+        c.step(128)
+        secs = timed_steps(c, steps, torch)
+        c.close()
+        mlups = 256 * 256 * steps / secs / 1e6
+        out[dt] = {"mlups": round(mlups, 1),
+                   "effective_GBps": round(mlups * 1e6 * bpn / 1e9, 1)}
+    return out
+
+
 def calib_copy(mib, torch):
     n = mib * (1 << 20) // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -150,6 +247,14 @@ def main():
     cav.close()
     del cav
     torch.cuda.empty_cache()
+    if not args.no_extras:
+        print("# batched leg", file=sys.stderr, flush=True)
+        result["batched"] = leg_batched(torch)
+        print("# adjoint leg", file=sys.stderr, flush=True)
+        result["adjoint"] = leg_adjoint(torch)
+        print("# 256^2 FP32/FP64 leg", file=sys.stderr, flush=True)
+        result["porous256"] = leg_porous256(torch)
+        result["batched"]["vs_roofline_run"] = round(result["batched"]["value"] / mlups, 3)
     if not args.no_cpu:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(w)

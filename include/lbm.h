@@ -175,6 +175,10 @@ lbm_status lbm_batch_step(lbm_ctx* c, int64_t nsteps);
 /* Observables of every cavity (synchronises); o has n entries. */
 lbm_status lbm_batch_observables(lbm_ctx* c, lbm_obs* o);
 
+/* Macroscopic fields of cavity i at the current time level (synchronises): optional device
+ * arrays [ny_i][nx_i] of the batch's dtype, as in lbm_observables. */
+lbm_status lbm_batch_fields(lbm_ctx* c, int32_t i, void* ux, void* uy, void* p, void* T);
+
 /* Launch shape in use: out[0] nodes per work-item along x, out[1] work-group size,
  * out[2] work-groups per step, out[3] steps per graph replay. */
 lbm_status lbm_batch_shape(const lbm_ctx* c, int32_t* out);

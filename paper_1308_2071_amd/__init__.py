@@ -21,7 +21,7 @@ __all__ = [
     "lbm_default_params", "lbm_derived", "lbm_workspace_size", "lbm_init", "lbm_step",
     "lbm_observables", "lbm_grad", "lbm_state_size", "lbm_save", "lbm_load", "lbm_destroy",
     "lbm_batch_workspace_size", "lbm_batch_init", "lbm_batch_step", "lbm_batch_observables",
-    "lbm_batch_shape", "lbm_status_string", "lbm_last_error", "Cavity", "Batch", "NuHot",
+    "lbm_batch_fields", "lbm_batch_shape", "lbm_status_string", "lbm_last_error", "Cavity", "Batch", "NuHot",
 ]
 
 _ARRAY_FIELDS = ("bc", "T_wall", "ext_accel")
@@ -131,6 +131,11 @@ def lbm_batch_observables(ctx: int, n: int):
     if s not in (_abi.LBM_OK, _abi.LBM_E_DIVERGED):
         check(s, "lbm_batch_observables")
     return s, list(o)
+
+
+def lbm_batch_fields(ctx: int, i: int, ux=None, uy=None, p=None, T=None) -> None:
+    check(library().lbm_batch_fields(ctx, int(i), ptr(ux), ptr(uy), ptr(p), ptr(T)),
+          "lbm_batch_fields")
 
 
 def lbm_batch_shape(ctx: int):

@@ -79,6 +79,7 @@ def library() -> C.CDLL:
         "lbm_batch_init": [C.POINTER(vp), i32, P, C.POINTER(C.c_double), vp, sz, vp, C.c_char_p],
         "lbm_batch_step": [vp, i64],
         "lbm_batch_observables": [vp, C.POINTER(LbmObs)],
+        "lbm_batch_fields": [vp, i32, vp, vp, vp, vp],
         "lbm_batch_shape": [vp, C.POINTER(i32)],
     }
     for name, args in sig.items():
@@ -97,7 +98,7 @@ EXPORTED = (
     "lbm_default_params", "lbm_derived", "lbm_workspace_size", "lbm_init", "lbm_step",
     "lbm_observables", "lbm_grad", "lbm_state_size", "lbm_save", "lbm_load", "lbm_destroy",
     "lbm_batch_workspace_size", "lbm_batch_init", "lbm_batch_step", "lbm_batch_observables",
-    "lbm_batch_shape", "lbm_status_string", "lbm_last_error",
+    "lbm_batch_fields", "lbm_batch_shape", "lbm_status_string", "lbm_last_error",
 )
 
 

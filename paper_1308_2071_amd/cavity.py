@@ -5,7 +5,8 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import (LBM_FP64, lbm_batch_init, lbm_batch_observables, lbm_batch_shape,
+from . import (LBM_FP64, lbm_batch_fields, lbm_batch_init, lbm_batch_observables,
+               lbm_batch_shape,
                lbm_batch_step, lbm_batch_workspace_size, lbm_destroy, lbm_grad, lbm_init,
                lbm_load, lbm_observables, lbm_save, lbm_state_size, lbm_step, lbm_workspace_size,
                make_params)
@@ -100,6 +101,13 @@ class Batch:
         s, obs = lbm_batch_observables(self.ctx, self.n)
         return s, [_obs_dict(o) for o in obs]
 
+    def fields(self, i: int) -> dict:
+        p = self.params[i]
+        dt = _torch_dtype(p)
+        ux, uy, pr, T = (torch.empty(p.ny, p.nx, dtype=dt, device=self.device) for _ in range(4))
+        lbm_batch_fields(self.ctx, i, ux, uy, pr, T)
+        return dict(ux=ux, uy=uy, p=pr, T=T)
+
     def shape(self):
         return lbm_batch_shape(self.ctx)
 
@@ -134,8 +142,5 @@ class NuHot(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, gJ):
-        cav = ctx.cav
-        gphi, gK = cav.grad(float(gJ))
-        cav.close()
-        ctx.cav = None
+        gphi, gK = ctx.cav.grad(float(gJ))   # repeatable: the tape stays until ctx is freed
         return gphi.to(ctx.dtypes[0]), gK.to(ctx.dtypes[1]), None, None, None

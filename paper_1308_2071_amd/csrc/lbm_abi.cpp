@@ -235,11 +235,14 @@ struct lbm_ctx {
     // batched form
     int ncav = 0;
     std::vector<lbm_params> bp;
-    std::vector<double> bphi;
-    std::vector<BatchCavity> bcav;
-    size_t b_off_cav = 0, b_off_phys = 0, b_off_obs = 0;
-    int b_ntiles = 0;
-    int b_shape[4] = {0, 0, 0, 0};
+    std::vector<Geo> bG;
+    std::vector<Phys<float>> bP32;
+    std::vector<Phys<double>> bP64;
+    std::vector<long long> boff;      // element offset of each cavity in a state buffer
+    std::vector<double> bLdT;         // L / dT per cavity
+    size_t b_state_bytes = 0, b_off_buf[2] = {0, 0}, b_off_cav = 0, b_off_phys = 0;
+    size_t b_off_tiles = 0, b_off_part = 0, b_max_tiles = 0;
+    int b_wg = 4, b_npt = 1, b_nwg = 0, b_ntiles = 0;   // b_wg: rows per tile
 
     void* buf(int i) const { return ws + L.off_buf[i]; }
     void* medp() const { return med ? ws + L.off_med : nullptr; }
@@ -292,6 +295,273 @@ lbm_status ensure_graph(lbm_ctx* c, int start) {
         return hip_fail(e3, "graph instantiate");
     }
     c->gsteps = kGraphSteps;
+    return LBM_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// ---- batched form ------------------------------------------------------------------------
+
+constexpr int kBatchGraphSteps = 32;   // even: a replay ends on the buffer it started from
+constexpr int kBatchObsWG = 64;        // work-groups of one cavity's observables pass
+constexpr int kMinTileWidth = 64;      // narrowest tile of any supported launch shape
+
+struct BatchLayout {
+    std::vector<long long> off;
+    size_t state_bytes, off_buf[2], off_cav, off_phys, off_tiles, off_part, max_tiles, total;
+};
+
+lbm_status batch_layout(int32_t n, const lbm_params* p, BatchLayout* L) {
+    if (n <= 0) return fail(LBM_E_INVAL, "batch of %d cavities", n);
+    const int dt = p[0].dtype;
+    long long elems = 0;
+    size_t tiles = 0;
+    L->off.clear();
+    for (int i = 0; i < n; ++i) {
+        lbm_status s = validate(p[i]);
+        if (s != LBM_OK) return fail(s, "cavity %d: %s", i, g_err.c_str());
+        if (p[i].dtype != dt) return fail(LBM_E_INVAL, "cavity %d: dtypes differ in a batch", i);
+        if (p[i].checkpoint_every != 0)
+            return fail(LBM_E_UNSUPPORTED, "cavity %d: no adjoint tape in a batch", i);
+        const Geo G = make_geo(p[i]);
+        L->off.push_back(elems);
+        elems += (long long)kPlanes * G.plane;
+        elems = (elems + 63) / 64 * 64;  // 256-byte alignment in FP32
+        tiles += size_t(G.ny) * size_t((G.nx + kMinTileWidth - 1) / kMinTileWidth);
+    }
+    if (elems >= (1LL << 31))
+        return fail(LBM_E_INVAL, "batch state of %lld elements exceeds 2^31", elems);
+    if (tiles >= (size_t(1) << 31)) return fail(LBM_E_INVAL, "too many tiles");
+    const size_t esz = dt == LBM_FP64 ? 8 : 4;
+    L->state_bytes = align_up(size_t(elems) * esz);
+    size_t o = 0;
+    L->off_buf[0] = o;
+    o += L->state_bytes;
+    L->off_buf[1] = o;
+    o += L->state_bytes;
+    L->off_cav = o;
+    o += align_up(n * sizeof(BatchCavity));
+    L->off_phys = o;
+    o += align_up(n * std::max(sizeof(Phys<float>), sizeof(Phys<double>)));
+    L->off_tiles = o;
+    L->max_tiles = tiles;
+    o += align_up(tiles * sizeof(int));
+    L->off_part = o;
+    o += align_up(size_t(n) * (3 * kBatchObsWG + 8) * sizeof(double));
+    L->total = o;
+    return LBM_OK;
+}
+
+hipError_t batch_rest(lbm_ctx* c) {
+    const bool f64 = c->p.dtype == LBM_FP64;
+    const size_t esz = f64 ? 8 : 4;
+    for (int b = 0; b < 2; ++b) {
+        char* base = c->ws + c->b_off_buf[b];
+        for (int i = 0; i < c->ncav; ++i) {
+            const lbm_params& p = c->bp[i];
+            const Derived d = derive(p);
+            const double g0 = (1.0 - p.varpi) / 5.0 * (p.T_init - d.T0);
+            const double g1 = (4.0 + p.varpi) / 20.0 * (p.T_init - d.T0);
+            void* dst = base + size_t(c->boff[i]) * esz;
+            hipError_t e = f64 ? launch_rest<double>(dst, c->bG[i], g0, g1, c->stream)
+                               : launch_rest<float>(dst, c->bG[i], g0, g1, c->stream);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+// Tile queue for tiles of w nodes along x by h rows: fills the cavity table and the
+// tile -> cavity table.
+hipError_t batch_tables(lbm_ctx* c, int w, int h) {
+    std::vector<BatchCavity> cav(c->ncav);
+    std::vector<int> tc;
+    tc.reserve(c->b_max_tiles);
+    for (int i = 0; i < c->ncav; ++i) {
+        cav[i].G = c->bG[i];
+        cav[i].off = c->boff[i];
+        cav[i].tile0 = int(tc.size());
+        cav[i].tiles_x = (c->bG[i].nx + w - 1) / w;
+        const size_t nt = size_t(cav[i].tiles_x) * size_t((c->bG[i].ny + h - 1) / h);
+        tc.insert(tc.end(), nt, i);
+    }
+    if (tc.size() > c->b_max_tiles) return hipErrorInvalidValue;
+    c->b_ntiles = int(tc.size());
+    hipError_t e = hipMemcpy(c->ws + c->b_off_cav, cav.data(), cav.size() * sizeof(BatchCavity),
+                             hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+    return hipMemcpy(c->ws + c->b_off_tiles, tc.data(), tc.size() * sizeof(int),
+                     hipMemcpyHostToDevice);
+}
+
+template <typename R>
+BatchTable<R> batch_table(const lbm_ctx* c) {
+    BatchTable<R> T;
+    T.cav = (const BatchCavity*)(c->ws + c->b_off_cav);
+    T.phys = (const Phys<R>*)(c->ws + c->b_off_phys);
+    T.tile_cav = (const int*)(c->ws + c->b_off_tiles);
+    T.ncav = c->ncav;
+    T.ntiles = c->b_ntiles;
+    return T;
+}
+
+hipError_t batch_step_once(lbm_ctx* c, int from, hipStream_t s) {
+    const void* src = c->ws + c->b_off_buf[from];
+    void* dst = c->ws + c->b_off_buf[1 - from];
+    if (c->p.dtype == LBM_FP64)
+        return launch_batch_step<double>(src, dst, batch_table<double>(c), c->b_npt, c->b_wg,
+                                         c->b_nwg, s);
+    return launch_batch_step<float>(src, dst, batch_table<float>(c), c->b_npt, c->b_wg,
+                                    c->b_nwg, s);
+}
+
+lbm_status ensure_batch_graph(lbm_ctx* c, int start) {
+    if (c->gexec[start]) return LBM_OK;
+    if (!c->cap) HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking), "stream create");
+    HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal), "begin capture");
+    hipError_t err = hipSuccess;
+    int b = start;
+    for (int k = 0; k < kBatchGraphSteps && err == hipSuccess; ++k) {
+        err = batch_step_once(c, b, c->cap);
+        b = 1 - b;
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(c->cap, &graph);
+    if (err != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(err, "captured batch launch");
+    }
+    if (e2 != hipSuccess) return hip_fail(e2, "end capture");
+    hipError_t e3 = hipGraphInstantiate(&c->gexec[start], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e3 != hipSuccess) {
+        c->gexec[start] = nullptr;
+        return hip_fail(e3, "graph instantiate");
+    }
+    return LBM_OK;
+}
+
+// Cache key: device architecture, dtype and the list of cavity shapes.
+std::string batch_key(const lbm_ctx* c) {
+    hipDeviceProp_t prop;
+    int dev = 0;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        arch = prop.gcnArchName;
+    for (char& ch : arch)
+        if (ch == ' ' || ch == ':') ch = '_';
+    uint64_t h = 1469598103934665603ULL;  // FNV-1a over the shapes
+    auto mix = [&h](uint64_t v) {
+        for (int k = 0; k < 8; ++k) {
+            h ^= (v >> (8 * k)) & 0xff;
+            h *= 1099511628211ULL;
+        }
+    };
+    mix(uint64_t(c->ncav));
+    for (const Geo& G : c->bG) {
+        mix(uint64_t(G.nx));
+        mix(uint64_t(G.ny));
+    }
+    char buf[128];
+    snprintf(buf, sizeof buf, "%s|%s|%016llx", arch.c_str(),
+             c->p.dtype == LBM_FP64 ? "fp64" : "fp32", (unsigned long long)h);
+    return buf;
+}
+
+bool cache_lookup(const char* path, const std::string& key, int* wg, int* npt, int* nwg) {
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    char k[256];
+    int a, b, d;
+    bool found = false;
+    while (std::fscanf(f, "%255s %d %d %d", k, &a, &b, &d) == 4)
+        if (key == k) {
+            *wg = a;
+            *npt = b;
+            *nwg = d;
+            found = true;
+        }
+    std::fclose(f);
+    return found;
+}
+
+void cache_store(const char* path, const std::string& key, int wg, int npt, int nwg) {
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d %d\n", key.c_str(), wg, npt, nwg);
+    std::fclose(f);
+}
+
+// Autotuner: times every supported tile shape (rows per work-group x 64-node segments per
+// work-item) with one tile per work-group and with chunked persistent grids of 2..16
+// work-groups per CU, on the batch itself, and keeps the fastest.  The result is cached per
+// (device, dtype, cavity shapes) in tune_cache_path.
+lbm_status batch_tune(lbm_ctx* c, const char* path) {
+    int cu = 256;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
+    const std::string key = batch_key(c);
+    int rows, npt, nwg;
+    if (path && cache_lookup(path, key, &rows, &npt, &nwg)) {
+        c->b_wg = rows;
+        c->b_npt = npt;
+        HIP_TRY(batch_tables(c, 64 * npt, rows), "tile tables");
+        c->b_nwg = nwg > 0 ? nwg : c->b_ntiles;
+        return LBM_OK;
+    }
+    if (!path) {
+        c->b_wg = 4;
+        c->b_npt = 1;
+        HIP_TRY(batch_tables(c, 64, 4), "tile tables");
+        c->b_nwg = c->b_ntiles;
+        return LBM_OK;
+    }
+    const int shapes[8][2] = {{1, 1}, {1, 2}, {1, 4}, {2, 1}, {2, 2}, {4, 1}, {4, 2}, {8, 1}};
+    const int per_cu[5] = {0, 2, 4, 8, 16};  // 0: one tile per work-group
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "event");
+    HIP_TRY(hipEventCreate(&e1), "event");
+    float best = 1e30f;
+    int br = 4, bn = 1, bg = 0;
+    lbm_status st = LBM_OK;
+    for (const auto& sh : shapes) {
+        hipError_t e = batch_tables(c, 64 * sh[1], sh[0]);
+        if (e != hipSuccess) { st = hip_fail(e, "tile tables"); break; }
+        for (int pc : per_cu) {
+            c->b_wg = sh[0];
+            c->b_npt = sh[1];
+            c->b_nwg = pc == 0 ? c->b_ntiles : std::min(c->b_ntiles, pc * cu);
+            int from = 0;
+            for (int k = 0; k < 3 && e == hipSuccess; ++k, from = 1 - from)
+                e = batch_step_once(c, from, c->stream);
+            if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+            for (int k = 0; k < 10 && e == hipSuccess; ++k, from = 1 - from)
+                e = batch_step_once(c, from, c->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) { st = hip_fail(e, "autotune"); break; }
+            if (ms < best) {
+                best = ms;
+                br = sh[0];
+                bn = sh[1];
+                bg = pc == 0 ? 0 : c->b_nwg;
+            }
+        }
+        if (st != LBM_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != LBM_OK) return st;
+    c->b_wg = br;
+    c->b_npt = bn;
+    HIP_TRY(batch_tables(c, 64 * bn, br), "tile tables");
+    c->b_nwg = bg > 0 ? bg : c->b_ntiles;
+    cache_store(path, key, br, bn, bg);
     return LBM_OK;
 }
 
@@ -545,11 +815,57 @@ lbm_status lbm_load(lbm_ctx* c, const void* host_buf, size_t bytes) {
 lbm_status lbm_grad(lbm_ctx* c, double dJ, void* dJ_dphi, void* dJ_dK) {
     lbm_status s = check_ctx(c, false);
     if (s != LBM_OK) return s;
-    (void)dJ;
-    (void)dJ_dphi;
-    (void)dJ_dK;
-    if (c->p.checkpoint_every <= 0) return fail(LBM_E_STATE, "no adjoint tape (checkpoint_every = 0)");
-    return fail(LBM_E_UNSUPPORTED, "adjoint not built");
+    if (c->p.checkpoint_every <= 0)
+        return fail(LBM_E_STATE, "no adjoint tape (checkpoint_every = 0)");
+    if (!std::isfinite(dJ)) return fail(LBM_E_INVAL, "dJ is not finite");
+    const bool f64 = c->p.dtype == LBM_FP64;
+    const size_t esz = f64 ? 8 : 4;
+    const size_t nel = c->L.state_bytes / esz;
+    const int64_t N = c->step;
+    const int64_t C = c->p.checkpoint_every;
+    hipStream_t st = c->stream;
+    double* gphi = c->gacc(0);
+    double* gK = c->gacc(1);
+    HIP_TRY(launch_fill_f64(gphi, 2 * size_t(c->G.plane), st), "zero gradients");
+    HIP_TRY(f64 ? launch_fill<double>(c->lam(0), nel, st) : launch_fill<float>(c->lam(0), nel, st),
+            "zero adjoint");
+    HIP_TRY(f64 ? launch_fill<double>(c->lam(1), nel, st) : launch_fill<float>(c->lam(1), nel, st),
+            "zero adjoint");
+    int lc = 0;  // buffer holding the adjoint of the latest state
+    if (N > 0) {
+        const double LdT = c->d.L / c->d.dT;
+        HIP_TRY(f64 ? launch_adjoint_seed<double>(c->buf(c->cur), c->lam(lc), c->G, c->P64, LdT,
+                                                  st)
+                    : launch_adjoint_seed<float>(c->buf(c->cur), c->lam(lc), c->G, c->P32, LdT,
+                                                 st),
+                "adjoint seed");
+        const int64_t nseg = (N + C - 1) / C;
+        for (int64_t sg = nseg - 1; sg >= 0; --sg) {
+            const int64_t n0 = sg * C, len = std::min<int64_t>(C, N - n0);
+            // recompute X^{n0} .. X^{n0+len-1} from the checkpoint
+            HIP_TRY(hipMemcpyAsync(c->seg(0), c->ckpt(size_t(sg)), c->L.state_bytes,
+                                   hipMemcpyDeviceToDevice, st),
+                    "segment restore");
+            for (int64_t k = 1; k < len; ++k)
+                HIP_TRY(step_once(c, c->seg(size_t(k - 1)), c->seg(size_t(k)), st),
+                        "recompute launch");
+            for (int64_t k = len - 1; k >= 0; --k) {
+                const void* X = c->seg(size_t(k));
+                HIP_TRY(f64 ? launch_adjoint_step<double>(X, c->lam(lc), c->lam(1 - lc),
+                                                          c->medp(), gphi, gK, c->G, c->P64, st)
+                            : launch_adjoint_step<float>(X, c->lam(lc), c->lam(1 - lc),
+                                                         c->medp(), gphi, gK, c->G, c->P32, st),
+                        "adjoint step launch");
+                lc = 1 - lc;
+            }
+        }
+    }
+    if (dJ_dphi)
+        HIP_TRY(launch_unpitch_scale((double*)dJ_dphi, gphi, c->G, dJ, st), "gradient copy");
+    if (dJ_dK)
+        HIP_TRY(launch_unpitch_scale((double*)dJ_dK, gK, c->G, dJ, st), "gradient copy");
+    HIP_TRY(hipStreamSynchronize(st), "synchronize");
+    return LBM_OK;
 }
 
 lbm_status lbm_destroy(lbm_ctx* c) {
@@ -564,33 +880,176 @@ lbm_status lbm_destroy(lbm_ctx* c) {
 }
 
 lbm_status lbm_batch_workspace_size(int32_t n, const lbm_params* p, size_t* bytes) {
-    (void)n;
-    (void)p;
-    (void)bytes;
-    return fail(LBM_E_UNSUPPORTED, "batched form not built");
+    if (!p || !bytes) return fail(LBM_E_INVAL, "null argument");
+    BatchLayout L;
+    lbm_status s = batch_layout(n, p, &L);
+    if (s != LBM_OK) return s;
+    *bytes = L.total;
+    return LBM_OK;
 }
 
 lbm_status lbm_batch_init(lbm_ctx** out, int32_t n, const lbm_params* p,
                           const double* phi_uniform, void* workspace, size_t ws_bytes,
                           void* hip_stream, const char* tune_cache_path) {
-    (void)out; (void)n; (void)p; (void)phi_uniform; (void)workspace; (void)ws_bytes;
-    (void)hip_stream; (void)tune_cache_path;
-    return fail(LBM_E_UNSUPPORTED, "batched form not built");
+    if (!out || !p || !phi_uniform) return fail(LBM_E_INVAL, "null argument");
+    *out = nullptr;
+    BatchLayout L;
+    lbm_status s = batch_layout(n, p, &L);
+    if (s != LBM_OK) return s;
+    for (int i = 0; i < n; ++i)
+        if (!(phi_uniform[i] > 0 && phi_uniform[i] <= 1))
+            return fail(LBM_E_INVAL, "phi_uniform[%d] = %g outside (0, 1]", i, phi_uniform[i]);
+    if (!workspace) return fail(LBM_E_INVAL, "null workspace");
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+        return fail(LBM_E_INVAL, "workspace is not %zu-byte aligned", kAlign);
+    if (ws_bytes < L.total)
+        return fail(LBM_E_NOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, L.total);
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(LBM_E_NOMEM, "host allocation failed");
+    c->batch = true;
+    c->p = p[0];
+    c->ncav = n;
+    c->stream = (hipStream_t)hip_stream;
+    c->ws = (char*)workspace;
+    c->b_state_bytes = L.state_bytes;
+    c->b_off_buf[0] = L.off_buf[0];
+    c->b_off_buf[1] = L.off_buf[1];
+    c->b_off_cav = L.off_cav;
+    c->b_off_phys = L.off_phys;
+    c->b_off_tiles = L.off_tiles;
+    c->b_off_part = L.off_part;
+    c->b_max_tiles = L.max_tiles;
+    c->bp.assign(p, p + n);
+    c->boff = L.off;
+    for (int i = 0; i < n; ++i) {
+        const Derived d = derive(p[i]);
+        c->bG.push_back(make_geo(p[i]));
+        c->bP32.push_back(make_phys<float>(p[i], d, phi_uniform[i]));
+        c->bP64.push_back(make_phys<double>(p[i], d, phi_uniform[i]));
+        c->bLdT.push_back(d.L / d.dT);
+    }
+    const bool f64 = p[0].dtype == LBM_FP64;
+    hipError_t e = f64 ? hipMemcpy(c->ws + L.off_phys, c->bP64.data(), n * sizeof(Phys<double>),
+                                   hipMemcpyHostToDevice)
+                       : hipMemcpy(c->ws + L.off_phys, c->bP32.data(), n * sizeof(Phys<float>),
+                                   hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = batch_rest(c);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "lbm_batch_init");
+    }
+    s = batch_tune(c, tune_cache_path);
+    if (s == LBM_OK) {
+        hipError_t e2 = batch_rest(c);  // tuning stepped the cavities: back to rest
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(c->stream);
+        if (e2 != hipSuccess) s = hip_fail(e2, "lbm_batch_init");
+    }
+    if (s != LBM_OK) {
+        lbm_destroy(c);
+        return s;
+    }
+    c->step = 0;
+    c->cur = 0;
+    *out = c;
+    return LBM_OK;
 }
 
 lbm_status lbm_batch_step(lbm_ctx* c, int64_t nsteps) {
-    (void)c; (void)nsteps;
-    return fail(LBM_E_UNSUPPORTED, "batched form not built");
+    lbm_status s = check_ctx(c, true);
+    if (s != LBM_OK) return s;
+    if (nsteps < 0) return fail(LBM_E_INVAL, "nsteps < 0");
+    int64_t left = nsteps;
+    if (left >= kBatchGraphSteps) {
+        s = ensure_batch_graph(c, c->cur);
+        if (s != LBM_OK) return s;
+        while (left >= kBatchGraphSteps) {
+            HIP_TRY(hipGraphLaunch(c->gexec[c->cur], c->stream), "graph launch");
+            left -= kBatchGraphSteps;
+            c->step += kBatchGraphSteps;
+        }
+    }
+    for (; left > 0; --left) {
+        HIP_TRY(batch_step_once(c, c->cur, c->stream), "batch step launch");
+        c->cur = 1 - c->cur;
+        c->step += 1;
+    }
+    return LBM_OK;
 }
 
 lbm_status lbm_batch_observables(lbm_ctx* c, lbm_obs* o) {
-    (void)c; (void)o;
-    return fail(LBM_E_UNSUPPORTED, "batched form not built");
+    lbm_status s = check_ctx(c, true);
+    if (s != LBM_OK) return s;
+    if (!o) return fail(LBM_E_INVAL, "null lbm_obs");
+    const int n = c->ncav;
+    const bool f64 = c->p.dtype == LBM_FP64;
+    const size_t esz = f64 ? 8 : 4;
+    double* part0 = (double*)(c->ws + c->b_off_part);
+    const size_t per = 3 * kBatchObsWG + 8;
+    char* base = c->ws + c->b_off_buf[c->cur];
+    for (int i = 0; i < n; ++i) {
+        const void* src = base + size_t(c->boff[i]) * esz;
+        double* part = part0 + i * per;
+        double* res = part + 3 * kBatchObsWG;
+        hipError_t e =
+            f64 ? launch_observe<double>(src, nullptr, c->bG[i], c->bP64[i], nullptr, nullptr,
+                                         nullptr, nullptr, part, kBatchObsWG, c->bLdT[i], res,
+                                         c->stream)
+                : launch_observe<float>(src, nullptr, c->bG[i], c->bP32[i], nullptr, nullptr,
+                                        nullptr, nullptr, part, kBatchObsWG, c->bLdT[i], res,
+                                        c->stream);
+        if (e != hipSuccess) return hip_fail(e, "batch observables launch");
+    }
+    std::vector<double> h(size_t(n) * per);
+    HIP_TRY(hipMemcpyAsync(h.data(), part0, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream),
+            "readback");
+    HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
+    bool any = false;
+    for (int i = 0; i < n; ++i) {
+        const double* r = h.data() + i * per + 3 * kBatchObsWG;
+        const double nn = double(c->bp[i].nx) * c->bp[i].ny;
+        o[i].nu_hot = r[0];
+        o[i].nu_cold = r[1];
+        o[i].max_speed = r[2];
+        o[i].mass_err = std::fabs(r[3]) / (nn * c->bp[i].rho0);
+        o[i].step = c->step;
+        o[i].diverged = (r[4] != 0.0 || !(r[2] <= std::sqrt(1.0 / 3.0)) || !std::isfinite(r[0]))
+                            ? 1
+                            : 0;
+        o[i].pad_ = 0;
+        any = any || o[i].diverged;
+    }
+    if (any) return fail(LBM_E_DIVERGED, "a cavity diverged at step %lld", (long long)c->step);
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_fields(lbm_ctx* c, int32_t i, void* ux, void* uy, void* p, void* T) {
+    lbm_status s = check_ctx(c, true);
+    if (s != LBM_OK) return s;
+    if (i < 0 || i >= c->ncav) return fail(LBM_E_INVAL, "cavity %d of %d", i, c->ncav);
+    const bool f64 = c->p.dtype == LBM_FP64;
+    const size_t esz = f64 ? 8 : 4;
+    const void* src = c->ws + c->b_off_buf[c->cur] + size_t(c->boff[i]) * esz;
+    double* part = (double*)(c->ws + c->b_off_part) + size_t(i) * (3 * kBatchObsWG + 8);
+    double* res = part + 3 * kBatchObsWG;
+    hipError_t e = f64 ? launch_observe<double>(src, nullptr, c->bG[i], c->bP64[i], ux, uy, p, T,
+                                                part, kBatchObsWG, c->bLdT[i], res, c->stream)
+                       : launch_observe<float>(src, nullptr, c->bG[i], c->bP32[i], ux, uy, p, T,
+                                               part, kBatchObsWG, c->bLdT[i], res, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "batch fields launch");
+    HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
+    return LBM_OK;
 }
 
 lbm_status lbm_batch_shape(const lbm_ctx* c, int32_t* out) {
-    (void)c; (void)out;
-    return fail(LBM_E_UNSUPPORTED, "batched form not built");
+    lbm_status s = check_ctx(c, true);
+    if (s != LBM_OK) return s;
+    if (!out) return fail(LBM_E_INVAL, "null argument");
+    out[0] = c->b_npt;
+    out[1] = 64 * c->b_wg;
+    out[2] = c->b_nwg;
+    out[3] = kBatchGraphSteps;
+    return LBM_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,101 @@
+// lbm_batch.hip -- one launch steps many independent cavities of uneven size and parameters.
+//
+// The cavities' states sit back to back in two population buffers.  The tiles of all cavities
+// form one queue (cavity by cavity, tile row by tile row).  A tile -> cavity table and
+// per-cavity geometry / parameter tables (read through the scalar cache: every work-item of a
+// tile belongs to the same cavity) give each tile its setting.
+// The per-node arithmetic is the plain step's (uniform medium per cavity), so every cavity's
+// result is bitwise that of its own plain run.
+#include "lbm_device.hpp"
+#include "lbm_internal.hpp"
+
+namespace lbm {
+
+// Tile = 64 * NPT consecutive nodes along x (one wavefront per 64) times TH rows (one
+// wavefront per row), so narrow cavities still fill every wavefront.  CHUNKED: each
+// work-group walks one contiguous run of the tile queue (consecutive tiles mostly share a
+// cavity, so its parameters stay in the scalar cache); otherwise one tile per work-group.
+template <typename R, int TH, int NPT, bool CHUNKED>
+__global__ __launch_bounds__(64 * TH) void batch_step_kernel(const R* __restrict__ src,
+                                                             R* __restrict__ dst,
+                                                             const BatchCavity* __restrict__ cav,
+                                                             const Phys<R>* __restrict__ phys,
+                                                             const int* __restrict__ tile_cav,
+                                                             int ntiles) {
+    int t0, t1;
+    if constexpr (CHUNKED) {
+        t0 = int((long long)ntiles * blockIdx.x / gridDim.x);
+        t1 = int((long long)ntiles * (blockIdx.x + 1) / gridDim.x);
+    } else {
+        t0 = blockIdx.x;
+        t1 = t0 + 1;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int t = t0; t < t1; ++t) {
+        const int c = tile_cav[t];
+        const BatchCavity C = cav[c];
+        const Phys<R> P = phys[c];
+        const int lt = t - C.tile0;
+        const int ty = lt / C.tiles_x;
+        const int y = ty * TH + wave;
+        if (y >= C.G.ny) continue;
+        const int x0 = (lt - ty * C.tiles_x) * (64 * NPT) + lane;
+        const R* s = src + C.off;
+        R* d = dst + C.off;
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int x = x0 + k * 64;
+            if (x < C.G.nx) {
+                R f[9], g[5];
+                Mac<R> m;
+                Med<R> md;
+                node_state<R, false>(s, nullptr, C.G, P, x, y, f, g, m, md);
+                collide<R>(f, g, m, md, P);
+                const int o = y * C.G.pitch + x;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(f[i], d + i * C.G.plane + o);
+#pragma unroll
+                for (int i = 0; i < 5; ++i)
+                    __builtin_nontemporal_store(g[i], d + (9 + i) * C.G.plane + o);
+            }
+        }
+    }
+}
+
+template <typename R, int TH, int NPT>
+static hipError_t launch_v(const void* src, void* dst, const BatchTable<R>& T, int nwg,
+                           hipStream_t s) {
+    if (nwg >= T.ntiles)
+        batch_step_kernel<R, TH, NPT, false><<<T.ntiles, 64 * TH, 0, s>>>(
+            (const R*)src, (R*)dst, T.cav, T.phys, T.tile_cav, T.ntiles);
+    else
+        batch_step_kernel<R, TH, NPT, true><<<nwg, 64 * TH, 0, s>>>(
+            (const R*)src, (R*)dst, T.cav, T.phys, T.tile_cav, T.ntiles);
+    return hipGetLastError();
+}
+
+// Supported tile shapes: rows per work-group (work-group = 64 * rows work-items) and 64-node
+// segments per work-item along x; nwg >= ntiles launches one tile per work-group, fewer runs
+// the chunked persistent form.
+template <typename R>
+hipError_t launch_batch_step(const void* src, void* dst, const BatchTable<R>& T, int nodes_x,
+                             int rows, int nwg, hipStream_t s) {
+    switch (rows * 8 + nodes_x) {
+        case 1 * 8 + 1: return launch_v<R, 1, 1>(src, dst, T, nwg, s);
+        case 1 * 8 + 2: return launch_v<R, 1, 2>(src, dst, T, nwg, s);
+        case 1 * 8 + 4: return launch_v<R, 1, 4>(src, dst, T, nwg, s);
+        case 2 * 8 + 1: return launch_v<R, 2, 1>(src, dst, T, nwg, s);
+        case 2 * 8 + 2: return launch_v<R, 2, 2>(src, dst, T, nwg, s);
+        case 4 * 8 + 1: return launch_v<R, 4, 1>(src, dst, T, nwg, s);
+        case 4 * 8 + 2: return launch_v<R, 4, 2>(src, dst, T, nwg, s);
+        case 8 * 8 + 1: return launch_v<R, 8, 1>(src, dst, T, nwg, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_batch_step<float>(const void*, void*, const BatchTable<float>&, int,
+                                             int, int, hipStream_t);
+template hipError_t launch_batch_step<double>(const void*, void*, const BatchTable<double>&, int,
+                                              int, int, hipStream_t);
+
+}  // namespace lbm

@@ -294,12 +294,4 @@ __device__ __forceinline__ void node_state(const R* __restrict__ src, const R* _
     m.Fy = md.phi * (P.ay + P.gbeta * theta_b);
 }
 
-// Work-group id -> tile id such that each XCD (work-groups are dealt to the 8 XCDs round
-// robin) gets one contiguous run of tiles; neighbouring tiles then share an L2.
-__device__ __forceinline__ int xcd_tile(int wg, int nwg) {
-    const int q = nwg >> 3, r = nwg & 7;
-    const int xcd = wg & 7, k = wg >> 3;
-    return (xcd < r) ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
-}
-
 }  // namespace lbm

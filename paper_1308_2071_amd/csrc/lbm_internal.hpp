@@ -42,19 +42,22 @@ struct BatchCavity {
     Geo G;
     long long off;     // element offset of the cavity's state inside a state buffer
     int tile0;         // first tile id of the cavity
-    int tiles_x;       // tiles per row
+    int tiles_x;       // tiles along x
 };
 
 template <typename R>
 struct BatchTable {
     const BatchCavity* cav;  // device array [n]
     const Phys<R>* phys;     // device array [n]
+    const int* tile_cav;     // device array [ntiles]: cavity of each tile
     int ncav;
     int ntiles;
 };
 
+// rows: rows per tile (work-group = 64 * rows work-items); nodes_x: 64-node segments per
+// work-item along x; nwg >= ntiles: one tile per work-group, else chunked persistent.
 template <typename R>
 hipError_t launch_batch_step(const void* src, void* dst, const BatchTable<R>& T, int nodes_x,
-                             int wg_size, int nwg, hipStream_t s);
+                             int rows, int nwg, hipStream_t s);
 
 }  // namespace lbm

@@ -13,7 +13,10 @@ __global__ __launch_bounds__(kTileX) void step_kernel(const R* __restrict__ src,
                                                       R* __restrict__ dst,
                                                       const R* __restrict__ med, Geo G,
                                                       Phys<R> P, int tiles_x) {
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    // Work-groups in launch order walk the lattice row by row.  (Dealing each XCD one
+    // contiguous band of rows instead was measured 7% slower: it concentrates each XCD's
+    // stream on one address range.)
+    const int t = blockIdx.x;
     const int y = t / tiles_x;
     const int x = (t - y * tiles_x) * kTileX + threadIdx.x;
     if (x >= G.nx) return;

@@ -1,0 +1,135 @@
+"""The batched form: many cavities of uneven size and parameters stepped by one launch per step
+(replayed from a HIP graph), with the launch shape picked by the autotuner.
+
+Each cavity of a batch must equal its own plain run bitwise (the per-node arithmetic is the
+plain step's), and a subset is compared with the FP64 CPU oracle (1e-12 FP64 after short runs).
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import ref
+from paper_1308_2071_amd import Batch, Cavity, workloads
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("ux", "uy", "p", "T")
+
+
+def small_batch(dtype):
+    specs = [
+        (64, 64, 1e3, 1.0, 1e-2, 0.6),
+        (96, 40, 3e5, 0.71, 1e-3, 0.35),
+        (33, 70, 1e4, 7.0, 5e-2, 0.8),
+        (300, 17, 1e6, 1.0, 1e-4, 0.25),
+        (128, 128, 5e4, 0.71, 2e-2, 0.45),
+        (5, 5, 1e5, 1.0, 1e-2, 0.5),
+    ]
+    params, phis = [], []
+    for nx, ny, Ra, Pr, Da, phi in specs:
+        params.append(workloads.cavity(nx, ny, Ra=Ra, Pr=Pr, Da=Da, dtype=dtype))
+        phis.append(phi)
+    return params, phis
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+def test_batch_equals_standalone_runs_bitwise(dtype, tmp_path):
+    params, phis = small_batch(dtype)
+    b = Batch(params, phis, tune_cache_path=str(tmp_path / "tune.txt"))
+    b.step(150)           # graph replays + remainder
+    s, obs = b.observables()
+    assert s == 0
+    for i, (p, phi) in enumerate(zip(params, phis)):
+        c = Cavity(p, phi_uniform=phi)
+        c.step(150)
+        ref_obs = c.observables()
+        got = b.fields(i)
+        for k in FIELDS:
+            assert torch.equal(got[k], ref_obs[k]), (i, k)
+        assert obs[i]["nu_hot"] == ref_obs["nu_hot"]
+        assert obs[i]["step"] == 150
+        c.close()
+    b.close()
+
+
+def test_batch_subset_against_oracle():
+    params, phis = small_batch("fp64")
+    b = Batch(params, phis)
+    b.step(40)
+    for i in (0, 2, 3, 5):
+        p = dict(params[i])
+        p.pop("dtype")
+        lat = ref.RefLattice(phi_uniform=phis[i], **p)
+        lat.step(40)
+        r = lat.observables()
+        g = b.fields(i)
+        for k in FIELDS:
+            assert np.abs(g[k].cpu().numpy() - r[k]).max() <= 1e-12, (i, k)
+    b.close()
+
+
+def test_graph_replay_equals_single_steps():
+    params, phis = small_batch("fp32")
+    a = Batch(params, phis)
+    c = Batch(params, phis)
+    a.step(64)
+    for _ in range(64):
+        c.step(1)
+    for i in range(len(params)):
+        fa, fc = a.fields(i), c.fields(i)
+        for k in FIELDS:
+            assert torch.equal(fa[k], fc[k]), (i, k)
+
+
+def test_autotuner_caches_its_choice(tmp_path):
+    path = str(tmp_path / "tune.txt")
+    params, phis = small_batch("fp32")
+    a = Batch(params, phis, tune_cache_path=path)
+    shape = a.shape()
+    lines = open(path).read().splitlines()
+    assert len(lines) == 1 and lines[0].split()[0].startswith(("gfx", "unknown"))
+    b = Batch(params, phis, tune_cache_path=path)       # served from the cache
+    assert b.shape() == shape
+    assert len(open(path).read().splitlines()) == 1
+    # a different set of cavities gets its own entry
+    Batch(params[:3], phis[:3], tune_cache_path=path)
+    assert len(open(path).read().splitlines()) == 2
+    wg, npt = shape[1], shape[0]
+    assert wg in (64, 128, 256, 512) and npt in (1, 2, 4) and shape[3] % 2 == 0
+
+
+def test_batch_rejects_mixed_dtypes_and_tapes():
+    params, phis = small_batch("fp32")
+    bad = list(params)
+    bad[1] = dict(bad[1], dtype="fp64")
+    with pytest.raises(RuntimeError, match="LBM_E_INVAL"):
+        Batch(bad, phis)
+    bad = list(params)
+    bad[0] = dict(bad[0], checkpoint_every=10)
+    with pytest.raises(RuntimeError, match="LBM_E_UNSUPPORTED"):
+        Batch(bad, phis)
+
+
+def test_batch64_workload_runs_and_matches_plain_on_sampled_cavities(tmp_path):
+    """The 64-cavity workload at its full size for a few hundred steps: every cavity stays finite
+    and seven cavities (one per side length) equal their plain runs bitwise."""
+    cav = workloads.batch64()
+    params = [dict(c["params"], dtype="fp32") for c in cav]
+    phis = [c["phi"] for c in cav]
+    b = Batch(params, phis, tune_cache_path=str(tmp_path / "tune.txt"))
+    b.step(300)
+    s, obs = b.observables()
+    assert s == 0 and not any(o["diverged"] for o in obs)
+    seen = {}
+    for i, p in enumerate(params):
+        seen.setdefault(p["nx"], i)
+    for nx, i in sorted(seen.items()):
+        c = Cavity(params[i], phi_uniform=phis[i])
+        c.step(300)
+        r = c.observables()
+        g = b.fields(i)
+        for k in FIELDS:
+            assert torch.equal(g[k], r[k]), (nx, k)
+        c.close()
