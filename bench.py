@@ -28,9 +28,32 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 BYTES_PER_NODE_FP32 = 30 * 4   # 14 + 14 populations, phi, K
 BYTES_PER_NODE_FP32_UNIFORM = 28 * 4
 BYTES_PER_NODE_FP64_UNIFORM = 28 * 8
-# Profiled counters of the step kernel (FETCH_SIZE + WRITE_SIZE per launch, scaled by the
-# copy-kernel calibration); None until a profile of the current kernel is recorded.
-MEASURED_TRAFFIC_BYTES = None
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "step_kernel_fp32_4096_traffic.md")
+STEP_SOURCES = ("paper_1308_2071_amd/csrc/lbm_device.hpp", "paper_1308_2071_amd/csrc/lbm_kernels.hip",
+                "paper_1308_2071_amd/build.py")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the step kernel from the committed counter profile (FETCH_SIZE +
+    WRITE_SIZE, scaled by a plain copy's calibration), or None when the kernel's sources have
+    changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if ":" in line and line.strip().split(":")[0] in ("traffic_bytes_per_launch",
+                                                          "source_sha256"):
+            k, v = line.strip().split(":", 1)
+            vals[k] = v.strip()
+    m = hashlib.sha256()
+    for f in STEP_SOURCES:
+        m.update(open(os.path.join(ROOT, f), "rb").read())
+    if vals.get("source_sha256") != m.hexdigest() or "traffic_bytes_per_launch" not in vals:
+        return None
+    return int(vals["traffic_bytes_per_launch"])
 
 
 def parse():
@@ -240,7 +263,7 @@ def main():
         "hbm_pct": round(100.0 * achieved / HBM_PEAK_GBS, 2),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": MEASURED_TRAFFIC_BYTES,
+                     "traffic": measured_traffic(),
                      "bytes_per_node": BYTES_PER_NODE_FP32, "kernel": "step_kernel<float,true>"},
         "nu_hot": obs["nu_hot"], "diverged": obs["diverged"],
     }

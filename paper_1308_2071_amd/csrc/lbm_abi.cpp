@@ -519,7 +519,8 @@ lbm_status batch_tune(lbm_ctx* c, const char* path) {
         c->b_nwg = c->b_ntiles;
         return LBM_OK;
     }
-    const int shapes[8][2] = {{1, 1}, {1, 2}, {1, 4}, {2, 1}, {2, 2}, {4, 1}, {4, 2}, {8, 1}};
+    const int shapes[10][2] = {{1, 1}, {1, 2}, {1, 4}, {2, 1}, {2, 2}, {2, 4},
+                               {4, 1}, {4, 2}, {4, 4}, {8, 1}};
     const int per_cu[5] = {0, 2, 4, 8, 16};  // 0: one tile per work-group
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "event");

@@ -86,8 +86,10 @@ hipError_t launch_batch_step(const void* src, void* dst, const BatchTable<R>& T,
         case 1 * 8 + 4: return launch_v<R, 1, 4>(src, dst, T, nwg, s);
         case 2 * 8 + 1: return launch_v<R, 2, 1>(src, dst, T, nwg, s);
         case 2 * 8 + 2: return launch_v<R, 2, 2>(src, dst, T, nwg, s);
+        case 2 * 8 + 4: return launch_v<R, 2, 4>(src, dst, T, nwg, s);
         case 4 * 8 + 1: return launch_v<R, 4, 1>(src, dst, T, nwg, s);
         case 4 * 8 + 2: return launch_v<R, 4, 2>(src, dst, T, nwg, s);
+        case 4 * 8 + 4: return launch_v<R, 4, 4>(src, dst, T, nwg, s);
         case 8 * 8 + 1: return launch_v<R, 8, 1>(src, dst, T, nwg, s);
         default: return hipErrorInvalidValue;
     }

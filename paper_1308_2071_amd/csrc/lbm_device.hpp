@@ -252,13 +252,15 @@ __device__ __forceinline__ void collide(R f[9], R g[5], const Mac<R>& m, const M
 template <typename R>
 __device__ __forceinline__ R wall_theta(bool onW, bool onE, bool onS, bool onN, R theta_f,
                                         const Phys<R>& P) {
-    const int sx = onW ? 0 : (onE ? 1 : -1);
-    const int sy = onS ? 2 : (onN ? 3 : -1);
-    const bool isoX = sx >= 0 && P.iso[sx];
-    const bool isoY = sy >= 0 && P.iso[sy];
-    if (isoX && isoY) return R(0.5) * (P.theta_wall[sx] + P.theta_wall[sy]);
-    if (isoX) return P.theta_wall[sx];
-    if (isoY) return P.theta_wall[sy];
+    // selects, not indexing: a runtime index into P would force a register copy of it into
+    // private memory
+    const bool isoX = (onW && P.iso[0]) || (onE && P.iso[1]);
+    const bool isoY = (onS && P.iso[2]) || (onN && P.iso[3]);
+    const R tX = onW ? P.theta_wall[0] : P.theta_wall[1];
+    const R tY = onS ? P.theta_wall[2] : P.theta_wall[3];
+    if (isoX && isoY) return R(0.5) * (tX + tY);
+    if (isoX) return tX;
+    if (isoY) return tY;
     return theta_f;
 }
 
