@@ -81,6 +81,10 @@ typedef struct {
     double ext_accel[2];     /* extra body acceleration added to G of Eq. (4) (0 by default)  */
     double tau_v, tau_T;     /* > 0 overrides Eq. (37b); otherwise derived from Ma, Ra, Pr, J */
     double gbeta;            /* >= 0 overrides g*beta; negative: Ma^2 cs^2 / (dT L)           */
+    double Ra_I;             /* internal Rayleigh number (Sec. 2); > 0: heat source Q''' from  */
+                             /* Ra_I = g beta Q''' L^5 / (nu alpha_e^2); with Ra = 0 it also   */
+                             /* sets tau_v (Sec. 4.2) and the scale dT = Q''' L^2/alpha_e = 1 */
+    double Qv;               /* Q''' in lattice units when Ra_I <= 0 (default 0: no source)   */
     int32_t dtype;           /* LBM_FP32 or LBM_FP64                                          */
     int32_t checkpoint_every;/* 0: no adjoint tape; C > 0: checkpoint every C steps, lbm_grad on */
 } lbm_params;
@@ -106,7 +110,8 @@ lbm_status lbm_default_params(lbm_params* p);
  *  out[0] L = nx - 1, out[1] tau_v (Eq. (37b)), out[2] tau_T (Eq. (37b) with nu = nu_e / J, so
  *  that Pr = nu / alpha_e and alpha_e = sigma csT^2 (tau_T - 1/2), Eq. (A9)), out[3] nu_e
  *  (Eq. (24)), out[4] nu, out[5] g*beta (Ma = U / cs, U = sqrt(g beta dT L)), out[6] dT,
- *  out[7] T0, out[8] K = Da L^2 (infinite when Da <= 0).  out has room for 9 doubles. */
+ *  out[7] T0, out[8] K = Da L^2 (infinite when Da <= 0), out[9] the heat source Q''' (Eq. (30)).
+ *  out has room for 10 doubles. */
 lbm_status lbm_derived(const lbm_params* p, double* out);
 
 /* Bytes of device workspace lbm_init needs for *p; with checkpoint_every > 0 the adjoint tape
@@ -118,6 +123,8 @@ lbm_status lbm_workspace_size(const lbm_params* p, int64_t nsteps_max, size_t* b
  * phi then takes phi_uniform everywhere, K takes Da L^2 everywhere (no Darcy or Forchheimer
  * drag when Da <= 0).  The library copies them into the workspace; the caller may free them
  * after the call returns.  The cavity starts at rest (see State semantics).
+ * With Ra_I > 0 or Qv != 0 the thermal step carries the heat source: Psi of Eq. (30) enters the
+ * collision through (I - Theta/2) Psi (Eqs. (33), (34)) and T = sum g + Q'''/(2 sigma) (Eq. (36)).
  * Errors: LBM_E_INVAL for nx or ny below 5 on a walled axis (the five-point stencil of
  * Eq. (38) needs five nodes) or below 2 on a periodic one, unpaired periodic sides, a
  * derived tau_v or tau_T not above 1/2, phi_uniform outside (0, 1], varpi >= 1 (Eq. (29)),
@@ -135,6 +142,12 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps);
  * phi_b p_b = phi_f p_f), T (Eq. (36)).  Returns LBM_E_DIVERGED with o->diverged = 1 when a
  * field is not finite or max |u| exceeds cs. */
 lbm_status lbm_observables(lbm_ctx* c, lbm_obs* o, void* ux, void* uy, void* p, void* T);
+
+/* Stream function at the current time level (synchronises): psi (device array [ny][nx] of the
+ * context's dtype) with u_x = d psi / dy, integrated along y by the trapezoid rule from psi = 0
+ * at y = 0 (the south side), from the velocity of Eq. (21); its maximum normalised by
+ * L sqrt(g beta dT L) is the psi_max of Sec. 4.2 (Table 3). */
+lbm_status lbm_stream_function(lbm_ctx* c, void* psi);
 
 /* Discrete adjoint (synchronises).  For J = nu_hot at the current time level n (Eq. (38)),
  * computes dJ_dphi = dJ * dJ/dphi(x) and dJ_dK = dJ * dJ/dK(x) at every node, the exact

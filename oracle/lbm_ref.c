@@ -11,7 +11,7 @@
  * What it computes (paper section / equation in brackets):
  *   flow    : D2Q9 MRT collision in moment space with porosity-dependent equilibrium moments and
  *             a moment-space forcing term [Sec. 3.1, Eqs. (6)-(24)];
- *   heat    : D2Q5 MRT collision without heat source [Sec. 3.2, Eqs. (26)-(37a)];
+ *   heat    : D2Q5 MRT collision with the heat source term [Sec. 3.2, Eqs. (26)-(37a)];
  *   walls   : non-equilibrium extrapolation for both distributions [Sec. 4, ref. 43];
  *   output  : macroscopic u, p, T and the wall-averaged Nusselt numbers [Eq. (38)].
  *
@@ -60,14 +60,17 @@ typedef struct {
     double tau_v, tau_T;     /* > 0: use this value; otherwise Eq. (37b)                       */
     double gbeta;            /* >= 0: use this value; negative: from Ma                        */
     int32_t uniform_rates;   /* 1: every flow rate 1/tau_v and every thermal rate 1/tau_T      */
+    double Ra_I;             /* internal Rayleigh number (Sec. 2); > 0: Q''' derived from it   */
+    double Qv;               /* Q''' in lattice units when Ra_I <= 0 (0: no heat source)      */
 } ref_params;
 
 /* Derived quantities, in this order, for the tests:
- * 0 L, 1 cs2, 2 csT2, 3 tau_v, 4 tau_T, 5 nu_e, 6 nu, 7 gbeta, 8 dT, 9 T0, 10 K_uniform      */
-#define REF_NDERIVED 11
+ * 0 L, 1 cs2, 2 csT2, 3 tau_v, 4 tau_T, 5 nu_e, 6 nu, 7 gbeta, 8 dT, 9 T0, 10 K_uniform,
+ * 11 Q (the heat source Q''')                                                               */
+#define REF_NDERIVED 12
 
 typedef struct {
-    double L, cs2, csT2, tau_v, tau_T, nu_e, nu, gbeta, dT, T0, K_uniform;
+    double L, cs2, csT2, tau_v, tau_T, nu_e, nu, gbeta, dT, T0, K_uniform, Q;
     double s[9], zeta[5];
 } ref_derived;
 
@@ -154,15 +157,22 @@ void ref_default_params(ref_params *p) {
     p->tau_T = -1;
     p->gbeta = -1;
     p->uniform_rates = 0;
+    p->Ra_I = 0.0;
+    p->Qv = 0.0;
 }
 
 static void derive(const ref_params *p, ref_derived *d) {
     d->L = (double)(p->nx - 1);
     d->cs2 = 1.0 / 3.0;                  /* cs = c / sqrt(3), after Eq. (13)  */
     d->csT2 = (4.0 + p->varpi) / 10.0;   /* after Eq. (37a)                   */
-    /* Eq. (37b): tau_v = 1/2 + Ma J L sqrt(Pr/Ra) / (cs dt) */
-    d->tau_v = p->tau_v > 0 ? p->tau_v
-                            : 0.5 + p->Ma * p->J * d->L * sqrt(p->Pr / p->Ra) / sqrt(d->cs2);
+    /* Eq. (37b): tau_v = 1/2 + Ma J L sqrt(Pr/Ra) / (cs dt); with internal heating only
+     * (Ra = 0, Sec. 4.2) Ra_I takes Ra's place */
+    if (p->tau_v > 0)
+        d->tau_v = p->tau_v;
+    else if (p->Ra > 0)
+        d->tau_v = 0.5 + p->Ma * p->J * d->L * sqrt(p->Pr / p->Ra) / sqrt(d->cs2);
+    else
+        d->tau_v = 0.5 + p->Ma * p->J * d->L * sqrt(p->Pr) / (sqrt(d->cs2) * sqrt(p->Ra_I));
     d->nu_e = d->cs2 * (d->tau_v - 0.5); /* Eq. (24) */
     d->nu = d->nu_e / p->J;              /* J = nu_e / nu, Sec. 2 */
     /* alpha_e = sigma csT^2 (tau_T - 1/2) (after Eq. (37a), Eq. (A9)) and Pr = nu / alpha_e */
@@ -178,6 +188,15 @@ static void derive(const ref_params *p, ref_derived *d) {
     /* Ma = U / cs with U = sqrt(g beta dT L), Sec. 4 */
     d->gbeta = p->gbeta >= 0 ? p->gbeta : p->Ma * p->Ma * d->cs2 / (d->dT * d->L);
     d->K_uniform = p->Da > 0 ? p->Da * d->L * d->L : INFINITY; /* Da = K / L^2, Sec. 2 */
+    /* Heat source: Ra_I = g beta Q''' L^5 / (nu alpha_e^2) (Sec. 2) with
+     * alpha_e = sigma csT^2 (tau_T - 1/2) (after Eq. (37a)).  Without side heating the
+     * temperature scale is dT = Q''' L^2 / alpha_e (Sec. 4.2), taken as 1. */
+    if (p->Ra_I > 0) {
+        const double alpha = p->sigma * d->csT2 * (d->tau_T - 0.5);
+        d->Q = p->Ra_I * d->nu * alpha * alpha / (d->gbeta * pow(d->L, 5.0));
+    } else {
+        d->Q = p->Qv;
+    }
 
     /* Eq. (20) with the values of Sec. 4; Eq. (31) likewise. */
     const double sv = 1.0 / d->tau_v, sT = 1.0 / d->tau_T;
@@ -196,7 +215,7 @@ void ref_derive(const ref_params *p, double *out) {
     ref_derived d;
     derive(p, &d);
     const double v[REF_NDERIVED] = {d.L,  d.cs2,   d.csT2, d.tau_v, d.tau_T,    d.nu_e,
-                                    d.nu, d.gbeta, d.dT,   d.T0,    d.K_uniform};
+                                    d.nu, d.gbeta, d.dT,   d.T0,    d.K_uniform, d.Q};
     memcpy(out, v, sizeof v);
 }
 
@@ -280,7 +299,8 @@ static void interior_macros(const double fh[9], const double gh[5], double phi, 
                             const ref_params *p, const ref_derived *d, macro_t *m) {
     const double rho0 = p->rho0;
     double T = 0.0;
-    for (int i = 0; i < 5; ++i) T += gh[i];                        /* Eq. (36), Q''' = 0 */
+    for (int i = 0; i < 5; ++i) T += gh[i];
+    T += 0.5 * d->Q / p->sigma;                                    /* Eq. (36), dt = 1 */
     const double Gx = p->ext_accel[0];
     const double Gy = p->ext_accel[1] + d->gbeta * (T - d->T0);    /* G = g beta (T-T0) j */
     double jx = 0.0, jy = 0.0;
@@ -333,7 +353,9 @@ static void collide_node(const double fh[9], const double gh[5], const macro_t *
         for (int i = 0; i < 5; ++i) n[k] += NN[k][i] * gh[i];            /* Eq. (27) */
     }
     neq(m->T, m->ux, m->uy, p->sigma, p->varpi, ne);
-    for (int k = 0; k < 5; ++k) np[k] = n[k] - d->zeta[k] * (n[k] - ne[k]); /* Eq. (34) */
+    const double Psi[5] = {d->Q / p->sigma, 0.0, 0.0, p->varpi * d->Q / p->sigma, 0.0}; /* (30) */
+    for (int k = 0; k < 5; ++k)                                         /* Eq. (34), dt = 1 */
+        np[k] = n[k] - d->zeta[k] * (n[k] - ne[k]) + (1.0 - 0.5 * d->zeta[k]) * Psi[k];
     for (int i = 0; i < 5; ++i) {
         gp[i] = 0.0;
         for (int k = 0; k < 5; ++k) gp[i] += NINV[i][k] * np[k];        /* g+ = N^-1 n+ */

@@ -32,11 +32,11 @@ DEFAULTS = dict(
     s_e=1.1, s_eps=1.1, s_q=1.2, zeta3=1.5, zeta4=1.5,
     forchheimer=1, T_init=0.5, ext_accel=(0.0, 0.0),
     tau_v=-1.0, tau_T=-1.0, gbeta=-1.0,
-    uniform_rates=0,
+    uniform_rates=0, Ra_I=0.0, Qv=0.0,
 )
 
 DERIVED_NAMES = ("L", "cs2", "csT2", "tau_v", "tau_T", "nu_e", "nu", "gbeta", "dT", "T0",
-                 "K_uniform")
+                 "K_uniform", "Q")
 
 
 class RefParams(C.Structure):
@@ -54,6 +54,7 @@ class RefParams(C.Structure):
         ("tau_v", C.c_double), ("tau_T", C.c_double),
         ("gbeta", C.c_double),
         ("uniform_rates", C.c_int32),
+        ("Ra_I", C.c_double), ("Qv", C.c_double),
     ]
 
 

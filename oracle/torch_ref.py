@@ -138,7 +138,7 @@ class TorchLattice:
     def _fluid_macros(self, fh, gh, phi, K):
         p, d = self.p, self.d
         rho0 = p["rho0"]
-        T = gh.sum(0)                                                      # Eq. (36)
+        T = gh.sum(0) + 0.5 * d["Q"] / p["sigma"]                         # Eq. (36)
         Gx = torch.full_like(T, p["ext_accel"][0])
         Gy = p["ext_accel"][1] + d["gbeta"] * (T - d["T0"])
         ex = torch.tensor(EX, dtype=DT).view(9, 1, 1)
@@ -239,7 +239,9 @@ class TorchLattice:
         fp = (MINV @ mp.reshape(9, n)).reshape(9, self.ny, self.nx)
         nm = (N @ gh.reshape(5, n)).reshape(5, self.ny, self.nx)
         ne = torch.stack([T, ux * T / sigma, uy * T / sigma, varpi * T, torch.zeros_like(T)])  # Eq. (29)
-        np_ = nm - self.z * (nm - ne)                                      # Eq. (34)
+        Q = self.d["Q"]
+        psi = torch.tensor([Q / sigma, 0.0, 0.0, varpi * Q / sigma, 0.0], dtype=DT).view(5, 1, 1)
+        np_ = nm - self.z * (nm - ne) + (1 - 0.5 * self.z) * psi           # Eqs. (30), (34)
         gp = (NINV @ np_.reshape(5, n)).reshape(5, self.ny, self.nx)
         return fp, gp
 
@@ -277,7 +279,8 @@ class TorchLattice:
         while done < nsteps:
             k = nsteps - done if segment <= 0 else min(segment, nsteps - done)
             if segment > 0 and torch.is_grad_enabled():
-                f, g = checkpoint(self._segment, f, g, phi, K, k, use_reentrant=False)
+                # reentrant form: the non-reentrant one keeps every step's intermediates here
+                f, g = checkpoint(self._segment, f, g, phi, K, k, use_reentrant=True)
             else:
                 f, g = self._segment(f, g, phi, K, k)
             done += k

@@ -19,7 +19,7 @@ __all__ = [
     "LbmParams", "LbmObs", "LbmError", "LBM_FP32", "LBM_FP64", "LBM_WALL_ISOTHERMAL",
     "LBM_WALL_ADIABATIC", "LBM_PERIODIC", "library", "make_params", "params_dict",
     "lbm_default_params", "lbm_derived", "lbm_workspace_size", "lbm_init", "lbm_step",
-    "lbm_observables", "lbm_grad", "lbm_state_size", "lbm_save", "lbm_load", "lbm_destroy",
+    "lbm_observables", "lbm_grad", "lbm_stream_function", "lbm_state_size", "lbm_save", "lbm_load", "lbm_destroy",
     "lbm_batch_workspace_size", "lbm_batch_init", "lbm_batch_step", "lbm_batch_observables",
     "lbm_batch_fields", "lbm_batch_shape", "lbm_status_string", "lbm_last_error", "Cavity", "Batch", "NuHot",
 ]
@@ -36,9 +36,9 @@ def lbm_default_params() -> LbmParams:
 
 
 def lbm_derived(p: LbmParams) -> dict:
-    out = (C.c_double * 9)()
+    out = (C.c_double * 10)()
     check(library().lbm_derived(C.byref(p), out), "lbm_derived")
-    names = ("L", "tau_v", "tau_T", "nu_e", "nu", "gbeta", "dT", "T0", "K")
+    names = ("L", "tau_v", "tau_T", "nu_e", "nu", "gbeta", "dT", "T0", "K", "Q")
     return dict(zip(names, list(out)))
 
 
@@ -76,6 +76,10 @@ def lbm_observables(ctx: int, ux=None, uy=None, p=None, T=None):
 
 def lbm_grad(ctx: int, dJ: float, dJ_dphi=None, dJ_dK=None) -> None:
     check(library().lbm_grad(ctx, float(dJ), ptr(dJ_dphi), ptr(dJ_dK)), "lbm_grad")
+
+
+def lbm_stream_function(ctx: int, psi) -> None:
+    check(library().lbm_stream_function(ctx, ptr(psi)), "lbm_stream_function")
 
 
 def lbm_state_size(ctx: int) -> int:

@@ -30,6 +30,7 @@ class LbmParams(C.Structure):
         ("ext_accel", C.c_double * 2),
         ("tau_v", C.c_double), ("tau_T", C.c_double),
         ("gbeta", C.c_double),
+        ("Ra_I", C.c_double), ("Qv", C.c_double),
         ("dtype", C.c_int32),
         ("checkpoint_every", C.c_int32),
     ]
@@ -71,6 +72,7 @@ def library() -> C.CDLL:
         "lbm_step": [vp, i64],
         "lbm_observables": [vp, C.POINTER(LbmObs), vp, vp, vp, vp],
         "lbm_grad": [vp, dbl, vp, vp],
+        "lbm_stream_function": [vp, vp],
         "lbm_state_size": [vp, C.POINTER(sz)],
         "lbm_save": [vp, vp, sz],
         "lbm_load": [vp, vp, sz],
@@ -96,7 +98,7 @@ def library() -> C.CDLL:
 
 EXPORTED = (
     "lbm_default_params", "lbm_derived", "lbm_workspace_size", "lbm_init", "lbm_step",
-    "lbm_observables", "lbm_grad", "lbm_state_size", "lbm_save", "lbm_load", "lbm_destroy",
+    "lbm_observables", "lbm_grad", "lbm_stream_function", "lbm_state_size", "lbm_save", "lbm_load", "lbm_destroy",
     "lbm_batch_workspace_size", "lbm_batch_init", "lbm_batch_step", "lbm_batch_observables",
     "lbm_batch_fields", "lbm_batch_shape", "lbm_status_string", "lbm_last_error",
 )

@@ -8,7 +8,8 @@ import torch
 from . import (LBM_FP64, lbm_batch_fields, lbm_batch_init, lbm_batch_observables,
                lbm_batch_shape,
                lbm_batch_step, lbm_batch_workspace_size, lbm_destroy, lbm_grad, lbm_init,
-               lbm_load, lbm_observables, lbm_save, lbm_state_size, lbm_step, lbm_workspace_size,
+               lbm_load, lbm_observables, lbm_save, lbm_state_size, lbm_step, lbm_stream_function,
+               lbm_workspace_size,
                make_params)
 from ._abi import LBM_OK, LbmParams
 
@@ -65,6 +66,11 @@ class Cavity:
         if fields:
             d.update(ux=ux, uy=uy, p=p, T=T)
         return d
+
+    def stream_function(self):
+        psi = torch.empty(self.ny, self.nx, dtype=self.dtype, device=self.device)
+        lbm_stream_function(self.ctx, psi)
+        return psi
 
     def grad(self, dJ: float = 1.0):
         gphi = torch.empty(self.ny, self.nx, dtype=torch.float64, device=self.device)

@@ -47,7 +47,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Parameters of Sec. 4 derived from the problem statement.
 struct Derived {
-    double L, cs2, csT2, tau_v, tau_T, nu_e, nu, gbeta, dT, T0, K;
+    double L, cs2, csT2, tau_v, tau_T, nu_e, nu, gbeta, dT, T0, K, Q;
 };
 
 Derived derive(const lbm_params& p) {
@@ -56,7 +56,9 @@ Derived derive(const lbm_params& p) {
     d.cs2 = 1.0 / 3.0;
     d.csT2 = (4.0 + p.varpi) / 10.0;
     // Eq. (37b)
-    d.tau_v = p.tau_v > 0 ? p.tau_v : 0.5 + p.Ma * p.J * d.L * std::sqrt(p.Pr / p.Ra) *
+    // with internal heating only (Ra = 0, Sec. 4.2) Ra_I takes Ra's place
+    const double Ra_eff = p.Ra > 0 ? p.Ra : p.Ra_I;
+    d.tau_v = p.tau_v > 0 ? p.tau_v : 0.5 + p.Ma * p.J * d.L * std::sqrt(p.Pr / Ra_eff) *
                                                 std::sqrt(3.0);
     d.nu_e = d.cs2 * (d.tau_v - 0.5);  // Eq. (24)
     d.nu = d.nu_e / p.J;               // J = nu_e / nu
@@ -70,6 +72,9 @@ Derived derive(const lbm_params& p) {
     // Ma = U / cs with U = sqrt(g beta dT L)
     d.gbeta = p.gbeta >= 0 ? p.gbeta : p.Ma * p.Ma * d.cs2 / (d.dT * d.L);
     d.K = p.Da > 0 ? p.Da * d.L * d.L : INFINITY;
+    // Ra_I = g beta Q''' L^5 / (nu alpha_e^2) with alpha_e = sigma csT^2 (tau_T - 1/2)
+    const double alpha = p.sigma * d.csT2 * (d.tau_T - 0.5);
+    d.Q = p.Ra_I > 0 ? p.Ra_I * d.nu * alpha * alpha / (d.gbeta * std::pow(d.L, 5.0)) : p.Qv;
     return d;
 }
 
@@ -96,8 +101,9 @@ lbm_status validate(const lbm_params& p) {
         return fail(LBM_E_INVAL, "rho0, sigma and J must be positive");
     if (!(p.varpi < 1) || !(p.varpi > -4))
         return fail(LBM_E_INVAL, "varpi = %g must lie in (-4, 1) (Eq. (29))", p.varpi);
-    if (p.tau_v <= 0 && (!(p.Ra > 0) || !(p.Pr > 0) || !(p.Ma > 0)))
-        return fail(LBM_E_INVAL, "Ra, Pr and Ma must be positive to derive tau_v");
+    if (p.tau_v <= 0 && (!(p.Ra > 0 || p.Ra_I > 0) || !(p.Pr > 0) || !(p.Ma > 0)))
+        return fail(LBM_E_INVAL, "Ra (or Ra_I), Pr and Ma must be positive to derive tau_v");
+    if (p.Ra_I < 0 || !std::isfinite(p.Qv)) return fail(LBM_E_INVAL, "bad heat source");
     if (p.tau_T <= 0 && !(p.Pr > 0))
         return fail(LBM_E_INVAL, "Pr must be positive to derive tau_T");
     if (p.checkpoint_every < 0) return fail(LBM_E_INVAL, "checkpoint_every must be >= 0");
@@ -107,6 +113,8 @@ lbm_status validate(const lbm_params& p) {
     if (!(d.tau_T > 0.5) || !std::isfinite(d.tau_T))
         return fail(LBM_E_INVAL, "tau_T = %.17g must exceed 1/2", d.tau_T);
     if (!std::isfinite(d.gbeta)) return fail(LBM_E_INVAL, "g*beta is not finite");
+    if (p.Ra_I > 0 && !(d.gbeta > 0)) return fail(LBM_E_INVAL, "Ra_I needs g*beta > 0");
+    if (!std::isfinite(d.Q)) return fail(LBM_E_INVAL, "heat source is not finite");
     const double rates[5] = {p.s_e, p.s_eps, p.s_q, p.zeta3, p.zeta4};
     for (double r : rates)
         if (!(r > 0 && r < 2)) return fail(LBM_E_INVAL, "relaxation rate %g outside (0, 2)", r);
@@ -152,6 +160,9 @@ Phys<R> make_phys(const lbm_params& p, const Derived& d, double phi_u) {
     P.wt1 = R((4.0 + p.varpi) / 20.0);
     P.u_coef = R(1.0 / (p.sigma * d.csT2));
     P.T0 = R(d.T0);
+    // heat source, Eqs. (30), (34), (36): Psi0 = Q/sigma, Psi3 = varpi Q/sigma
+    P.hQs = R(0.5 * d.Q / p.sigma);
+    P.psi3 = R((1.0 - 0.5 * p.zeta3) * p.varpi * d.Q / p.sigma);
     for (int s = 0; s < 4; ++s) {
         P.theta_wall[s] = R(p.T_wall[s] - d.T0);
         P.iso[s] = p.bc[s] == LBM_WALL_ISOTHERMAL;
@@ -614,6 +625,8 @@ lbm_status lbm_default_params(lbm_params* p) {
     p->tau_v = -1.0;
     p->tau_T = -1.0;
     p->gbeta = -1.0;
+    p->Ra_I = 0.0;
+    p->Qv = 0.0;
     p->dtype = LBM_FP32;
     p->checkpoint_every = 0;
     g_err.clear();
@@ -623,7 +636,7 @@ lbm_status lbm_default_params(lbm_params* p) {
 lbm_status lbm_derived(const lbm_params* p, double* out) {
     if (!p || !out) return fail(LBM_E_INVAL, "null argument");
     const Derived d = derive(*p);
-    const double v[9] = {d.L, d.tau_v, d.tau_T, d.nu_e, d.nu, d.gbeta, d.dT, d.T0, d.K};
+    const double v[10] = {d.L, d.tau_v, d.tau_T, d.nu_e, d.nu, d.gbeta, d.dT, d.T0, d.K, d.Q};
     std::memcpy(out, v, sizeof v);
     return LBM_OK;
 }
@@ -767,6 +780,20 @@ lbm_status lbm_observables(lbm_ctx* c, lbm_obs* o, void* ux, void* uy, void* p, 
                       : 0;
     o->pad_ = 0;
     if (o->diverged) return fail(LBM_E_DIVERGED, "diverged at step %lld", (long long)c->step);
+    return LBM_OK;
+}
+
+lbm_status lbm_stream_function(lbm_ctx* c, void* psi) {
+    lbm_status s = check_ctx(c, false);
+    if (s != LBM_OK) return s;
+    if (!psi) return fail(LBM_E_INVAL, "null psi");
+    hipError_t e = c->p.dtype == LBM_FP64
+                       ? launch_stream_function<double>(c->buf(c->cur), c->medp(), c->G, c->P64,
+                                                        psi, c->stream)
+                       : launch_stream_function<float>(c->buf(c->cur), c->medp(), c->G, c->P32,
+                                                       psi, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "stream function launch");
+    HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
     return LBM_OK;
 }
 

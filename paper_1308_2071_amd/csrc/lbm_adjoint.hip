@@ -115,7 +115,7 @@ __device__ __forceinline__ void macros_vjp(const R f[9], const R g[5], R phi, R 
                                            const MacAdj<R>& A0, R af[9], R ag[5], R& lphi,
                                            R& lK) {
     // forward recompute
-    const R theta = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
+    const R theta = ((g[0] + g[1]) + (g[2] + g[3]) + g[4]) + P.hQs;
     const R Gx = P.ax, Gy = P.ay + P.gbeta * theta;
     const R jx = (f[1] - f[3]) + (f[5] - f[6]) - (f[7] - f[8]);
     const R jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);

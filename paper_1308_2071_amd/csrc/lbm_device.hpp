@@ -39,6 +39,8 @@ struct Phys {
     R wt0, wt1;            // Eq. (37a) weights
     R u_coef;              // 1 / (sigma csT^2)
     R T0;
+    R hQs;                 // Q'''/(2 sigma): T = sum g + hQs (Eq. (36))
+    R psi3;                // (1 - zeta3/2) varpi Q'''/sigma (Eqs. (30), (34))
     R theta_wall[4];       // T_wall - T0 per side
     int iso[4];            // side is isothermal
     int forch;             // Forchheimer term on
@@ -115,7 +117,7 @@ template <typename R>
 __device__ __forceinline__ Mac<R> fluid_macros(const R f[9], const R g[5], const Med<R>& md,
                                                const Phys<R>& P) {
     Mac<R> m;
-    const R theta = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
+    const R theta = ((g[0] + g[1]) + (g[2] + g[3]) + g[4]) + P.hQs;
     const R Gx = P.ax;
     const R Gy = P.ay + P.gbeta * theta;
     const R jx = (f[1] - f[3]) + (f[5] - f[6]) - (f[7] - f[8]);
@@ -177,8 +179,8 @@ __device__ __forceinline__ void nee_wall(R f[9], R g[5], const Mac<R>& mf, const
 }
 
 // Collision in moment space, Eq. (17) with s0 = s3 = s5 = 1 (Sec. 4) and Eq. (34) with
-// zeta0 = 1, no heat source; f, g hold post-streaming deviations on entry and post-collision
-// deviations on exit.
+// zeta0 = 1 and the heat source of Eq. (30); f, g hold post-streaming deviations on entry and
+// post-collision deviations on exit.
 template <typename R>
 __device__ __forceinline__ void collide(R f[9], R g[5], const Mac<R>& m, const Med<R>& md,
                                         const Phys<R>& P) {
@@ -228,16 +230,17 @@ __device__ __forceinline__ void collide(R f[9], R g[5], const Mac<R>& m, const M
     f[7] = c58 - px - py + a8;
     f[8] = c58 + px - py - a8;
 
-    // thermal: n' = N g' (rows of Eq. (28)); n0' = theta is conserved (zeta0 = 1)
+    // thermal: n' = N g' (rows of Eq. (28)); with zeta0 = 1, n0'+ = theta + Q'''/(2 sigma)
+    // (the source term of Eq. (34) with Psi0 = Q'''/sigma, Eq. (30))
     const R T = P.T0 + m.theta;
     const R n1 = g[1] - g[3];
     const R n2 = g[2] - g[4];
     const R n3 = (g[1] + g[2]) + (g[3] + g[4]) - R(4) * g[0];
     const R n4 = (g[1] - g[2]) + (g[3] - g[4]);
-    const R b0 = m.theta * R(0.2);
+    const R b0 = (m.theta + P.hQs) * R(0.2);
     const R b1 = (n1 - P.z_T * (n1 - ux * T * P.inv_sigma)) * R(0.5);
     const R b2 = (n2 - P.z_T * (n2 - uy * T * P.inv_sigma)) * R(0.5);
-    const R b3 = (n3 - P.z3 * (n3 - P.varpi * m.theta)) * R(0.05);
+    const R b3 = (n3 - P.z3 * (n3 - P.varpi * m.theta) + P.psi3) * R(0.05);
     const R b4 = (n4 - P.z4 * n4) * R(0.25);
     // g' = N^T b (columns of Eq. (28))
     g[0] = b0 - R(4) * b3;

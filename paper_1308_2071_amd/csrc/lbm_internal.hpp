@@ -19,6 +19,9 @@ hipError_t launch_observe(const void* src, const void* med, const Geo& G, const 
                           void* ux, void* uy, void* p, void* T, double* part, int nparts,
                           double L_over_dT, double* out, hipStream_t s);
 template <typename R>
+hipError_t launch_stream_function(const void* src, const void* med, const Geo& G,
+                                  const Phys<R>& P, void* psi, hipStream_t s);
+template <typename R>
 hipError_t launch_rest(void* dst, const Geo& G, double g0, double g1, hipStream_t s);
 template <typename R>
 hipError_t launch_pitch_copy(void* dst, const void* src, const Geo& G, double v, hipStream_t s);

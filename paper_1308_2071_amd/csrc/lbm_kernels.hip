@@ -114,7 +114,7 @@ __device__ __forceinline__ double node_theta(const R* __restrict__ src, const Ge
     const int yf = y + (onS ? 1 : 0) - (onN ? 1 : 0);
     R f[9], g[5];
     pull<R>(src, G, xf, yf, f, g);
-    const R th = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
+    const R th = ((g[0] + g[1]) + (g[2] + g[3]) + g[4]) + P.hQs;
     if (!(onW || onE || onS || onN)) return double(th);
     return double(wall_theta<R>(onW, onE, onS, onN, th, P));
 }
@@ -177,6 +177,26 @@ __global__ __launch_bounds__(256) void nusselt_kernel(const R* __restrict__ src,
     }
 }
 
+// Stream function: one work-item per column x integrates u_x (Eq. (21)) along y with the
+// trapezoid rule, psi(x, 0) = 0.
+template <typename R, bool PN>
+__global__ void stream_function_kernel(const R* __restrict__ src, const R* __restrict__ med,
+                                       Geo G, Phys<R> P, R* __restrict__ psi) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= G.nx) return;
+    double acc = 0.0, prev = 0.0;
+    for (int y = 0; y < G.ny; ++y) {
+        R f[9], g[5];
+        Mac<R> m;
+        Med<R> md;
+        node_state<R, PN>(src, med, G, P, x, y, f, g, m, md);
+        const double u = double(m.ux);
+        if (y > 0) acc += 0.5 * (prev + u);
+        prev = u;
+        psi[y * G.nx + x] = R(acc);
+    }
+}
+
 // Rest state (u = 0, phi p = rho0 cs^2, T = T_init) as deviations: f' = 0, g' = wt (T_init - T0).
 template <typename R>
 __global__ void rest_kernel(R* __restrict__ dst, Geo G, R g0, R g1) {
@@ -233,6 +253,19 @@ hipError_t launch_observe(const void* src, const void* med, const Geo& G, const 
 }
 
 template <typename R>
+hipError_t launch_stream_function(const void* src, const void* med, const Geo& G,
+                                  const Phys<R>& P, void* psi, hipStream_t s) {
+    const int nb = (G.nx + 63) / 64;
+    if (med)
+        stream_function_kernel<R, true><<<nb, 64, 0, s>>>((const R*)src, (const R*)med, G, P,
+                                                          (R*)psi);
+    else
+        stream_function_kernel<R, false><<<nb, 64, 0, s>>>((const R*)src, nullptr, G, P,
+                                                           (R*)psi);
+    return hipGetLastError();
+}
+
+template <typename R>
 hipError_t launch_rest(void* dst, const Geo& G, double g0, double g1, hipStream_t s) {
     rest_kernel<R><<<1024, 256, 0, s>>>((R*)dst, G, R(g0), R(g1));
     return hipGetLastError();
@@ -254,6 +287,10 @@ template hipError_t launch_observe<float>(const void*, const void*, const Geo&,
 template hipError_t launch_observe<double>(const void*, const void*, const Geo&,
                                            const Phys<double>&, void*, void*, void*, void*,
                                            double*, int, double, double*, hipStream_t);
+template hipError_t launch_stream_function<float>(const void*, const void*, const Geo&,
+                                                  const Phys<float>&, void*, hipStream_t);
+template hipError_t launch_stream_function<double>(const void*, const void*, const Geo&,
+                                                   const Phys<double>&, void*, hipStream_t);
 template hipError_t launch_rest<float>(void*, const Geo&, double, double, hipStream_t);
 template hipError_t launch_rest<double>(void*, const Geo&, double, double, hipStream_t);
 template hipError_t launch_pitch_copy<float>(void*, const void*, const Geo&, double, hipStream_t);

@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported(lbm):
 def test_param_struct_layout_matches_header(lbm):
     # the ctypes mirror must have the C layout: 8-byte aligned doubles after int32 pairs
     from paper_1308_2071_amd._abi import LbmObs, LbmParams
-    assert C.sizeof(LbmParams) == 8 + 16 + 32 + 4 * 8 + 4 * 8 + 5 * 8 + 8 + 8 + 16 + 3 * 8 + 8
+    assert C.sizeof(LbmParams) == 8 + 16 + 32 + 4 * 8 + 4 * 8 + 5 * 8 + 8 + 8 + 16 + 3 * 8 + 2 * 8 + 8
     assert C.sizeof(LbmObs) == 48
 
 
@@ -54,11 +54,15 @@ def test_defaults_are_the_papers(lbm):
     dict(nx=256, ny=256, Ra=1e5, Pr=1.0, Da=1e-2),
     dict(nx=4096, ny=4096, Ra=1e6, Pr=0.71, Da=1e-3),
     dict(nx=100, ny=37, Ra=3e4, Pr=7.0, Da=-1.0, J=1.3, sigma=0.8, varpi=-1.0),
+    dict(nx=151, ny=151, Ra=1e5, Ra_I=1e3, Pr=0.7, Da=1e-2),
+    dict(nx=121, ny=121, Ra=0.0, Ra_I=6.4e5, Pr=7.0, bc=(0, 0, 0, 0), T_wall=(0.0, 0.0, 0.0, 0.0),
+         T_init=0.0, forchheimer=0, Da=-1.0),
+    dict(nx=20, ny=9, Ra=1e4, Qv=3e-5, sigma=1.2),
 ])
 def test_derived_parameters_match_oracle(lbm, oracle, case):
     d = lbm.lbm_derived(lbm.make_params(**case))
     r = oracle.derived(**case)
-    for k in ("L", "tau_v", "tau_T", "nu_e", "nu", "gbeta", "dT", "T0"):
+    for k in ("L", "tau_v", "tau_T", "nu_e", "nu", "gbeta", "dT", "T0", "Q"):
         assert d[k] == pytest.approx(r[k], rel=1e-14), k
     assert d["K"] == pytest.approx(r["K_uniform"], rel=1e-14) or (np.isinf(d["K"]) and
                                                                    np.isinf(r["K_uniform"]))
@@ -83,6 +87,8 @@ def status_of(lbm, **kw):
     dict(tau_v=0.5),                             # tau must exceed 1/2
     dict(tau_T=0.4),
     dict(Ra=-1.0),
+    dict(Ra=0.0),                                # neither Ra nor Ra_I
+    dict(Ra_I=-5.0),
     dict(dtype=5),
     dict(s_q=2.5),
     dict(checkpoint_every=-3),

@@ -142,3 +142,15 @@ def test_nuhot_chains_through_kozeny_carman():
     _, rphi, rK = torch_ref.grad_nu_hot(e0, Kr, steps, nx=nx, ny=ny, Ra=1e5, Pr=1.0)
     dK = 3 * e0 ** 2 * dp2 / (150 * (1 - e0) ** 2) + 2 * e0 ** 3 * dp2 / (150 * (1 - e0) ** 3)
     check(g, rphi + rK * dK, 1e-10, "total dJ/deps")
+
+
+def test_adjoint_with_heat_source():
+    """The adjoint of the step with the heat source of Eqs. (30), (34), (36) (Sec. 4.3 setting)."""
+    nx, ny, steps = 13, 11, 30
+    params = dict(nx=nx, ny=ny, Ra=1e5, Ra_I=1e5, Pr=0.7)
+    phi, K = workloads.random_medium(ny, nx, seed=44, K_lo=2.0, K_hi=20.0)
+    J, gphi, gK = gpu_grad(params, phi, K, steps, 7, "fp64")
+    Jr, rphi, rK = torch_ref.grad_nu_hot(phi, K, steps, **params)
+    assert abs(J - Jr) <= 1e-11 * max(1.0, abs(Jr))
+    check(gphi, rphi, 1e-9, "heat source dJ/dphi")
+    check(gK, rK, 1e-9, "heat source dJ/dK")

@@ -1,0 +1,133 @@
+"""The paper's own validation, reproduced on the GPU: every case on the paper's grid, stepped
+to steady state in one batched launch per step, against the "Present" values the paper prints
+(``tests/golden/paper_table*.txt``).
+
+- Tables 1 and 2 (Sec. 4.1): natural convection, hot-wall (Table 2) or cold-wall (Table 1)
+  average Nusselt number;
+- Table 4 (Sec. 4.3): side heating plus a uniform heat source (Eqs. (30), (33)-(36)): Nu and
+  theta_max;
+- Table 3 (Sec. 4.2): internal heating only, all walls cold: psi_max and theta_max.
+
+These check the whole model, the readings of the paper (wall reconstruction, L = nx - 1,
+g beta from Ma, tau from Eq. (37b), the heat source from Ra_I) included, against the paper's
+published results; they are context for the oracle parity tests, not a substitute.  The
+Da = 1e-6 rows of Tables 2 and 4 are left out: their Darcy-regime flow (|u| ~ 1e-3) needs ~1e7
+steps to settle.
+
+Table 1 cases: phi = 0.9999, Da = 1e8, Pr = 0.71, Ra 1e3..1e7 on 150^2 / 250^2; Table 2 cases:
+Da = 1e-2 and 1e-4, Pr = 1, phi 0.4 / 0.6 on 120^2 / 200^2.  Steady state: the largest relative
+change of any cavity's Nu over 20,000 steps falls below 1e-6 (or 2e6 steps pass).  Tolerance:
+1.5 % of the paper's value (the codes the paper compares with spread by up to 4 % on these rows).
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1308_2071_amd import Batch, workloads
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rows(name):
+    out = []
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                out.append(tuple(float(v) for v in line.split()))
+    return out
+
+
+def test_tables_1_and_2_at_steady_state():
+    grid2 = {1e-2: 120, 1e-4: 200}
+    cases = []
+    for Da, Ra, phi, nu in rows("paper_table2_nu.txt"):
+        if Da in grid2:
+            cases.append((f"Table 2 Da={Da:g} Ra={Ra:g} phi={phi:g}",
+                          workloads.cavity(grid2[Da], Ra=Ra, Pr=1.0, Da=Da, dtype="fp32"), phi,
+                          nu, "nu_hot"))
+    for Ra, nu in rows("paper_table1_nu.txt"):
+        g = 150 if Ra <= 1e4 else 250
+        cases.append((f"Table 1 Ra={Ra:g}", workloads.cavity(g, Ra=Ra, Pr=0.71, Da=1e8,
+                                                             dtype="fp32"), 0.9999, nu,
+                      "nu_cold"))
+    b = Batch([c[1] for c in cases], [c[2] for c in cases])
+    prev, steps, chunk = None, 0, 20000
+    while steps < 2_000_000:
+        b.step(chunk)
+        steps += chunk
+        s, obs = b.observables()
+        assert s == 0
+        nu = [o[c[4]] for o, c in zip(obs, cases)]
+        if prev is not None and max(abs(a - p) / abs(p) for a, p in zip(nu, prev)) < 1e-6:
+            break
+        prev = nu
+    report = []
+    for (name, _, _, ref, _), v in zip(cases, nu):
+        report.append(f"{name:32s} Nu {v:8.4f}  paper {ref:8.4f}  {100 * (v - ref) / ref:+.2f} %")
+    print(f"steady after {steps} steps\n" + "\n".join(report))
+    for (name, _, _, ref, _), v in zip(cases, nu):
+        assert abs(v - ref) <= 0.015 * ref, name
+
+
+def run_to_steady(b, n, chunk, max_steps, extra=None):
+    """Steps until the largest relative change of every cavity's Nu and max T over one chunk is
+    below 1e-6 (relative to max(|value|, 1e-3)), or max_steps pass."""
+    prev, steps = None, 0
+    while steps < max_steps:
+        b.step(chunk)
+        steps += chunk
+        s, obs = b.observables()
+        assert s == 0
+        cur = np.array([o["nu_hot"] for o in obs] +
+                       [float(b.fields(i)["T"].double().max()) for i in range(n)])
+        if prev is not None and np.max(np.abs(cur - prev) / np.maximum(np.abs(prev), 1e-3)) < 1e-6:
+            break
+        prev = cur
+    return steps, cur[:n], cur[n:]
+
+
+def test_table4_internal_and_side_heating():
+    """Sec. 4.3, Table 4: the heat source of Eqs. (30), (33)-(36) with side heating.  Nu within
+    1.5 % of |Nu| (0.02 absolute near zero) and theta_max = max (T - T0) within 3 %."""
+    cases = rows("paper_table4.txt")
+    params, phis = [], []
+    for Ra, RaI, Da, phi, nu, th in cases:
+        n = 150 if Ra == 1e5 else 200
+        params.append(workloads.cavity(n, Ra=Ra, Ra_I=RaI, Pr=0.7, Da=Da, dtype="fp32"))
+        phis.append(phi)
+    b = Batch(params, phis)
+    steps, nu, tmax = run_to_steady(b, len(cases), 20000, 2_000_000)
+    lines = []
+    for (Ra, RaI, Da, phi, pn, pt), v, t in zip(cases, nu, tmax):
+        lines.append(f"Ra={Ra:g} Ra_I={RaI:g} Da={Da:g}: Nu {v:9.4f} (paper {pn}), "
+                     f"theta_max {t - 0.5:7.4f} (paper {pt})")
+    print(f"steady after {steps} steps\n" + "\n".join(lines))
+    for (Ra, RaI, Da, phi, pn, pt), v, t in zip(cases, nu, tmax):
+        assert abs(v - pn) <= max(0.015 * abs(pn), 0.02), (Ra, RaI, Da, v, pn)
+        assert abs((t - 0.5) - pt) <= 0.03 * pt, (Ra, RaI, Da, t - 0.5, pt)
+
+
+def test_table3_internal_heating_cold_walls():
+    """Sec. 4.2, Table 3: all walls cold, Ra = 0, Ra_I = 6.4e5, Pr = 7, phi = 1, F_phi = 0, on a
+    120^2 grid.  psi_max / (L sqrt(g beta dT L)) within 2 % and theta_max within 2 %."""
+    cases = rows("paper_table3.txt")
+    params = [workloads.cavity(120, Ra=0.0, Ra_I=6.4e5, Pr=7.0, Da=Da, forchheimer=0,
+                               bc=(0, 0, 0, 0), T_wall=(0.0,) * 4, T_init=0.0, dtype="fp32")
+              for Da, _, _ in cases]
+    b = Batch(params, [1.0] * len(cases))
+    steps, _, tmax = run_to_steady(b, len(cases), 100000, 8_000_000)
+    U = 0.1 / np.sqrt(3.0)           # sqrt(g beta dT L) = Ma cs
+    for i, (Da, pp, pt) in enumerate(cases):
+        ux = b.fields(i)["ux"].double()
+        psi = torch.zeros_like(ux)
+        psi[1:] = torch.cumsum(0.5 * (ux[1:] + ux[:-1]), dim=0)
+        psi_max = float(psi.abs().max()) / (119 * U)
+        print(f"Da={Da:g}: psi_max {psi_max:.4e} (paper {pp:.3e}), theta_max {tmax[i]:.4e} "
+              f"(paper {pt:.3e}) after {steps} steps")
+        assert abs(psi_max - pp) <= 0.02 * pp, (Da, psi_max, pp)
+        assert abs(tmax[i] - pt) <= 0.02 * pt, (Da, tmax[i], pt)

@@ -156,3 +156,46 @@ def test_divergence_is_reported():
     cav.step(3)
     o = cav.observables(fields=False)
     assert o["diverged"] and o["status"] == -4
+
+
+HEAT_CASES = {
+    # Sec. 4.3: side heating plus internal heating
+    "side_and_internal": dict(nx=40, ny=33, Ra=1e5, Ra_I=1e5, Pr=0.7, Da=1e-2),
+    # Sec. 4.2: all walls cold, internal heating only, Brinkman-extended Darcy (phi = 1, F = 0)
+    "internal_only": dict(nx=37, ny=30, Ra=0.0, Ra_I=6.4e5, Pr=7.0, Da=1e-2, forchheimer=0,
+                          bc=(ISO, ISO, ISO, ISO), T_wall=(0.0, 0.0, 0.0, 0.0), T_init=0.0),
+    # a source given directly, adiabatic sides
+    "direct_source": dict(nx=30, ny=26, Ra=1e4, Pr=1.0, Qv=2e-5, sigma=1.3,
+                          bc=(ISO, ADIA, ADIA, ISO), T_wall=(1.0, 0.0, 0.0, 0.2)),
+}
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(HEAT_CASES))
+def test_heat_source_step_by_step(name, dtype):
+    """Eqs. (30), (33), (34), (36): the heat-source term against the oracle."""
+    params = HEAT_CASES[name]
+    ny, nx = params["ny"], params["nx"]
+    if name == "internal_only":
+        runs = run_pair(params, 0, phi_u=1.0, dtype=dtype, chunks=[1, 9, 90, 300])
+    else:
+        phi, K = workloads.random_medium(ny, nx, seed=nx + 7 * ny)
+        runs = run_pair(params, 0, phi=phi, K=K, dtype=dtype, chunks=[1, 9, 90, 300])
+    for i, (g, r) in enumerate(runs):
+        assert_match(g, r, dtype, what=f"{name} chunk {i}")
+
+
+def test_stream_function_integrates_the_oracle_velocity():
+    """psi with u_x = d psi / dy, trapezoid along y from psi = 0 on the south side, against the
+    same integral of the oracle's u_x (and u_y = -d psi / dx to second order in the interior)."""
+    params = dict(nx=48, ny=41, Ra=1e5, Pr=0.71, Da=1e-2)
+    cav = Cavity(dict(params, dtype="fp64"), phi_uniform=0.6)
+    lat = ref.RefLattice(phi_uniform=0.6, **params)
+    cav.step(400)
+    lat.step(400)
+    psi = cav.stream_function().cpu().numpy()
+    ux = lat.observables()["ux"]
+    want = np.zeros_like(ux)
+    want[1:] = np.cumsum(0.5 * (ux[1:] + ux[:-1]), axis=0)
+    assert np.abs(psi - want).max() <= 1e-12
+    assert np.abs(psi).max() > 1e-3

@@ -320,3 +320,64 @@ def test_porous_cavity_nusselt_against_table2(oracle):
     o = lat.observables()
     assert abs(o["nu_hot"] - target) < 0.01
     assert abs(o["nu_hot"] - o["nu_cold"]) < 1e-3
+
+
+def test_heat_source_energy_balance(oracle):
+    """Eqs. (30), (34), (36): with a uniform heat source Q''' and no flow, every node's
+    temperature rises by Q'''/sigma per step (sigma dT/dt = Q''', Eq. (3)); at t = 0 the
+    macroscopic T already carries the half-step shift Q'''/(2 sigma) of Eq. (36)."""
+    Q, sigma, n = 3e-4, 0.8, 200
+    P = dict(nx=6, ny=5, bc=P_ALL, gbeta=0.0, Qv=Q, sigma=sigma, T_init=0.25, tau_v=0.7,
+             tau_T=0.8)
+    lat = ref.RefLattice(phi_uniform=0.5, **P)
+    T0 = lat.observables()["T"]
+    np.testing.assert_allclose(T0, 0.25 + 0.5 * Q / sigma, atol=1e-15)
+    lat.step(n)
+    np.testing.assert_allclose(lat.observables()["T"], T0 + n * Q / sigma, atol=1e-13)
+
+
+def test_heat_source_conduction_profile(oracle):
+    """Steady conduction with a uniform source Q between two walls at T = 0 (Eq. (3) without
+    flow): alpha_e T'' = -Q, T = Q x (L - x) / (2 alpha_e), alpha_e = sigma csT^2 (tau_T - 1/2)
+    (Eq. (A9)).  The bulk scheme reproduces the quadratic exactly: the deviation from it is one
+    constant over all fluid nodes (an O(Q / alpha_e) offset from the wall reconstruction), and
+    relative to the profile it falls at second order in the lattice spacing."""
+    Q, sigma, tau_T = 2e-5, 1.3, 0.9
+    alpha = sigma * 0.2 * (tau_T - 0.5)
+    rel = []
+    for nx in (17, 33, 65):
+        P = dict(nx=nx, ny=4, bc=(ref.ISOTHERMAL, ref.ISOTHERMAL, ref.PERIODIC, ref.PERIODIC),
+                 T_wall=(0.0, 0.0, 0.0, 0.0), T_init=0.0, gbeta=0.0, Qv=Q, sigma=sigma,
+                 tau_v=0.8, tau_T=tau_T)
+        lat = ref.RefLattice(phi_uniform=0.7, **P)
+        L = nx - 1
+        lat.step(int(30 * L * L / (np.pi ** 2 * alpha / sigma)))
+        T = lat.observables()["T"][1]
+        x = np.arange(nx)
+        exact = Q * x * (L - x) / (2 * alpha)
+        dev = (T - exact)[1:-1]
+        assert np.ptp(dev) <= 1e-9 * exact.max()
+        assert abs(T[0]) < 1e-15 and abs(T[-1]) < 1e-15
+        rel.append(abs(dev.mean()) / exact.max())
+    assert rel[1] < 1e-3
+    orders = np.log2(np.array(rel[:-1]) / np.array(rel[1:]))
+    assert np.all(orders > 1.9), (rel, orders)
+
+
+def test_internal_rayleigh_number_definition(oracle):
+    """Sec. 2: Ra_I = g beta Q''' L^5 / (nu alpha_e^2); Sec. 4.2: tau_v from Ra_I when Ra = 0,
+    and dT = Q''' L^2 / alpha_e is the temperature scale (taken as 1)."""
+    d = ref.derived(nx=121, ny=121, Ra=0.0, Ra_I=6.4e5, Pr=7.0, bc=(0, 0, 0, 0),
+                    T_wall=(0.0, 0.0, 0.0, 0.0), T_init=0.0)
+    alpha = 0.2 * (d["tau_T"] - 0.5)
+    assert d["gbeta"] * d["Q"] * 120 ** 5 / (d["nu"] * alpha ** 2) == pytest.approx(6.4e5,
+                                                                                    rel=1e-12)
+    assert d["Q"] * 120 ** 2 / alpha == pytest.approx(1.0, rel=1e-12)
+    assert d["tau_v"] == pytest.approx(0.5 + 0.1 * 120 * np.sqrt(7.0 / 6.4e5) * np.sqrt(3.0),
+                                       rel=1e-14)
+    assert d["T0"] == 0.0
+    # Sec. 4.3: side heating sets dT = Th - Tc; Q''' then follows from Ra_I
+    d = ref.derived(nx=151, Ra=1e5, Ra_I=1e3, Pr=0.7, Da=1e-2)
+    alpha = 0.2 * (d["tau_T"] - 0.5)
+    assert d["gbeta"] * d["Q"] * 150 ** 5 / (d["nu"] * alpha ** 2) == pytest.approx(1e3,
+                                                                                   rel=1e-12)
