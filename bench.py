@@ -3,10 +3,12 @@
 
 Workload (the roofline run): 4096 x 4096 side-heated porous cavity, per-node porosity
 phi ~ U[0.3, 0.9] (seeded), Kozeny-Carman permeability with mean Da = 1e-3, Ra = 1e6, Pr = 0.71,
-FP32, inputs resident in HBM before timing.  A step is one fused time step of every node
-(pull streaming, wall reconstruction, macroscopics, flow and thermal MRT collision).
+FP32 storage, inputs resident in HBM before timing.  A step is one fused time step of every node
+(pull streaming, wall reconstruction, macroscopics, flow and thermal MRT collision), in FP32
+arithmetic (--dtype fp32, the default) or FP64 arithmetic on the same FP32 storage
+(--dtype fp32_f64); the other one is reported as an extra leg.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-extras]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--dtype D] [--no-cpu] [--no-extras]
 
 Prints one JSON line.  ``value`` is MLUPS (million lattice-node updates per second).  The
 ``roofline`` object prices the step kernel against HBM at its algorithmic bytes per node
@@ -62,6 +64,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--n", type=int, default=4096, help="grid side of the roofline workload")
+    ap.add_argument("--dtype", default="fp32", choices=("fp32", "fp32_f64"),
+                    help="roofline leg: FP32 storage with FP32 or FP64 arithmetic")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip batched / adjoint / FP64 legs")
     ap.add_argument("--calib-copy", type=int, default=0,
@@ -84,7 +88,6 @@ def timed_steps(cav, steps, torch):
 
 def cpu_baseline(w, budget_s=15.0):
     """FP64 CPU oracle on the same 4096^2 workload, as many whole steps as fit the budget."""
-    import numpy as np
     from oracle import ref
     cores = len(os.sched_getaffinity(0))
     ref.set_threads(cores)
@@ -92,13 +95,12 @@ def cpu_baseline(w, budget_s=15.0):
     t0 = time.perf_counter()
     lat.step(1)
     t1 = time.perf_counter() - t0
-    steps = max(1, min(50, int(budget_s / max(t1, 1e-6))))
+    steps = max(1, min(500, int(budget_s / max(t1, 1e-6))))
     t0 = time.perf_counter()
     lat.step(steps)
     dt = time.perf_counter() - t0
     n = w["params"]["nx"] * w["params"]["ny"]
     lat.close()
-    del np
     return {"value": round(n * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": cores,
             "kind": "oracle",
             "sample": f"{steps} FP64 steps of the full {w['params']['nx']}^2 workload "
@@ -186,20 +188,65 @@ def leg_adjoint(torch):
 
 
 def leg_porous256(torch, steps=2000):
-    """The 256^2 cavity (phi = 0.4, Da = 1e-2, Ra = 1e5, Pr = 1) in FP32 and FP64; its state is
-    cache-resident (3.7 / 7.3 MB per buffer), so its bandwidth is 'effective'."""
+    """The 256^2 cavity (phi = 0.4, Da = 1e-2, Ra = 1e5, Pr = 1) in FP32, FP32 storage with FP64
+    arithmetic, and FP64: MLUPS over `steps` (the state is cache-resident, 3.7 / 7.3 MB per
+    buffer, so its bandwidth is 'effective'), and the error after all 50k steps against the FP64
+    CPU oracle's values stored in tests/golden/porous256.npz (every 4th node): max |error| per
+    field over the oracle field's range (p less its rest value; FP32 storage also up to a
+    constant, the free pressure level), and |Nu_hot - oracle|."""
+    import numpy as np
     from paper_1308_2071_amd import Cavity, workloads
     w = workloads.porous256()
-    out = {"workload": "256x256, phi 0.4, Da 1e-2, Ra 1e5, Pr 1", "steps": steps}
-    for dt, bpn in (("fp32", BYTES_PER_NODE_FP32_UNIFORM), ("fp64", BYTES_PER_NODE_FP64_UNIFORM)):
+    gold = np.load(os.path.join(ROOT, "tests", "golden", "porous256.npz"))
+    out = {"workload": "256x256, phi 0.4, Da 1e-2, Ra 1e5, Pr 1", "steps": steps,
+           "error_after_steps": int(gold["steps"])}
+    for dt, bpn in (("fp32", BYTES_PER_NODE_FP32_UNIFORM),
+                    ("fp32_f64", BYTES_PER_NODE_FP32_UNIFORM),
+                    ("fp64", BYTES_PER_NODE_FP64_UNIFORM)):
         c = Cavity(dict(w["params"], dtype=dt), phi_uniform=w["phi"])
         c.step(128)
         secs = timed_steps(c, steps, torch)
         c.close()
         mlups = 256 * 256 * steps / secs / 1e6
+        c = Cavity(dict(w["params"], dtype=dt), phi_uniform=w["phi"])
+        c.step(int(gold["steps"]))
+        o = c.observables()
+        c.close()
+        err = {}
+        for k in ("ux", "uy", "p", "T"):
+            ref = gold[k] - (w["params"].get("rho0", 1.0) / 3.0 / w["phi"] if k == "p" else 0.0)
+            d = o[k].double().cpu().numpy()[::4, ::4] - ref
+            rng = float(gold[k + "_max"] - gold[k + "_min"])
+            err[k] = float(f"{np.abs(d).max() / rng:.3e}")
+            if k == "p" and dt != "fp64":
+                err["p_up_to_constant"] = float(f"{np.abs(d - d.mean()).max() / rng:.3e}")
         out[dt] = {"mlups": round(mlups, 1),
-                   "effective_GBps": round(mlups * 1e6 * bpn / 1e9, 1)}
+                   "effective_GBps": round(mlups * 1e6 * bpn / 1e9, 1),
+                   "nu_hot": o["nu_hot"], "nu_err": float(f"{abs(o['nu_hot'] - float(gold['nu_hot'])):.3e}"),
+                   "field_err_of_range": err}
+    out["oracle_nu_hot"] = float(gold["nu_hot"])
     return out
+
+
+KERNEL_NAME = {"fp32": "step_kernel<float,float,true>", "fp32_f64": "step_kernel<float,double,true>"}
+
+
+def roofline_run(torch, w, dtype, steps, warmup):
+    """The roofline workload (per-node phi and K, FP32 storage) stepped `steps` times after
+    `warmup`; achieved GB/s at the algorithmic 120 B per node update."""
+    from paper_1308_2071_amd import Cavity
+    nodes = w["params"]["nx"] * w["params"]["ny"]
+    phi32 = torch.tensor(w["phi"], dtype=torch.float32)
+    K32 = torch.tensor(w["K"], dtype=torch.float32)
+    cav = Cavity(dict(w["params"], dtype=dtype), phi=phi32, K=K32)
+    if warmup:
+        cav.step(warmup)
+    torch.cuda.synchronize()
+    secs = timed_steps(cav, steps, torch)
+    obs = cav.observables(fields=False)
+    cav.close()
+    return {"ms": secs / steps * 1e3, "mlups": nodes * steps / secs / 1e6,
+            "achieved": BYTES_PER_NODE_FP32 * nodes / (secs / steps) / 1e9, "obs": obs}
 
 
 def calib_copy(mib, torch):
@@ -219,9 +266,8 @@ def main():
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(see the sharding design notes); rerun with --gpus 1", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
-    from paper_1308_2071_amd import Cavity, workloads
+    from paper_1308_2071_amd import workloads
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.calib_copy:
         calib_copy(args.calib_copy, torch)
@@ -229,19 +275,9 @@ def main():
 
     w = workloads.roofline4096(args.n)
     nx, ny = w["params"]["nx"], w["params"]["ny"]
-    nodes = nx * ny
-    phi32 = torch.tensor(w["phi"], dtype=torch.float32)
-    K32 = torch.tensor(w["K"], dtype=torch.float32)
-    cav = Cavity(dict(w["params"], dtype="fp32"), phi=phi32, K=K32)
-    print(f"# workload {nx}x{ny} FP32, warmup {args.warmup}", file=sys.stderr, flush=True)
-    if args.warmup:
-        cav.step(args.warmup)
-    torch.cuda.synchronize()
-    secs = timed_steps(cav, args.steps, torch)
-    obs = cav.observables(fields=False)
-    ms = secs / args.steps * 1e3
-    mlups = nodes * args.steps / secs / 1e6
-    achieved = BYTES_PER_NODE_FP32 * nodes / (secs / args.steps) / 1e9
+    print(f"# workload {nx}x{ny} {args.dtype}, warmup {args.warmup}", file=sys.stderr, flush=True)
+    run = roofline_run(torch, w, args.dtype, args.steps, args.warmup)
+    ms, mlups, achieved, obs = run["ms"], run["mlups"], run["achieved"], run["obs"]
     print(f"# timed {args.steps} steps: {ms:.4f} ms/step, {mlups:.0f} MLUPS, "
           f"{achieved:.0f} GB/s", file=sys.stderr, flush=True)
     result = {
@@ -255,7 +291,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.dtype == "fp32" else "f64",
+        "storage": "f32",
         "data": "synthetic",
         "config": {"workload": f"porous cavity {nx}x{ny}, per-node phi~U[0.3,0.9], "
                                "Kozeny-Carman K (mean Da 1e-3), Ra 1e6, Pr 0.71",
@@ -263,12 +300,10 @@ def main():
         "hbm_pct": round(100.0 * achieved / HBM_PEAK_GBS, 2),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(),
-                     "bytes_per_node": BYTES_PER_NODE_FP32, "kernel": "step_kernel<float,true>"},
+                     "traffic": measured_traffic() if args.dtype == "fp32" else None,
+                     "bytes_per_node": BYTES_PER_NODE_FP32, "kernel": KERNEL_NAME[args.dtype]},
         "nu_hot": obs["nu_hot"], "diverged": obs["diverged"],
     }
-    cav.close()
-    del cav
     torch.cuda.empty_cache()
     if not args.no_extras:
         print("# batched leg", file=sys.stderr, flush=True)
@@ -277,12 +312,21 @@ def main():
         result["adjoint"] = leg_adjoint(torch)
         print("# 256^2 FP32/FP64 leg", file=sys.stderr, flush=True)
         result["porous256"] = leg_porous256(torch)
+        other = "fp32_f64" if args.dtype == "fp32" else "fp32"
+        print(f"# roofline workload in {other}", file=sys.stderr, flush=True)
+        o = roofline_run(torch, w, other, min(args.steps, 1000), args.warmup)
+        result["roofline_" + other] = {
+            "storage": "f32", "arithmetic": "f32" if other == "fp32" else "f64",
+            "steps": min(args.steps, 1000), "value": round(o["mlups"], 1), "unit": "MLUPS",
+            "ms_per_step": round(o["ms"], 5),
+            "hbm_pct": round(100.0 * o["achieved"] / HBM_PEAK_GBS, 2),
+            "kernel": KERNEL_NAME[other], "nu_hot": o["obs"]["nu_hot"],
+            "vs_headline": round(o["mlups"] / mlups, 3)}
         result["batched"]["vs_roofline_run"] = round(result["batched"]["value"] / mlups, 3)
     if not args.no_cpu:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(result), flush=True)
-    del np
 
 
 if __name__ == "__main__":

@@ -48,9 +48,13 @@ typedef int32_t lbm_status;
 #define LBM_E_STATE (-5)       /* call not valid in the context's current state             */
 #define LBM_E_UNSUPPORTED (-6) /* valid request this build does not implement               */
 
-/* Arithmetic of the populations and of every per-node operation. */
-#define LBM_FP32 0
-#define LBM_FP64 1
+/* Precision: storage of the populations, medium planes and fields, and the arithmetic of
+ * every per-node operation.  LBM_FP32_F64 stores FP32 (the bytes of LBM_FP32) and computes each
+ * step in FP64, rounding each stored value once per step; device arrays passed to or returned
+ * by the library (phi, K, fields) are FP32 for it. */
+#define LBM_FP32 0       /* FP32 storage, FP32 arithmetic */
+#define LBM_FP64 1       /* FP64 storage, FP64 arithmetic */
+#define LBM_FP32_F64 2   /* FP32 storage, FP64 arithmetic */
 
 /* Side conditions (Sec. 4.1, Fig. 1).  Velocity is no-slip on every non-periodic side.
  * Periodic sides come in pairs (west with east, south with north). */
@@ -85,7 +89,7 @@ typedef struct {
                              /* Ra_I = g beta Q''' L^5 / (nu alpha_e^2); with Ra = 0 it also   */
                              /* sets tau_v (Sec. 4.2) and the scale dT = Q''' L^2/alpha_e = 1 */
     double Qv;               /* Q''' in lattice units when Ra_I <= 0 (default 0: no source)   */
-    int32_t dtype;           /* LBM_FP32 or LBM_FP64                                          */
+    int32_t dtype;           /* LBM_FP32, LBM_FP64 or LBM_FP32_F64                            */
     int32_t checkpoint_every;/* 0: no adjoint tape; C > 0: checkpoint every C steps, lbm_grad on */
 } lbm_params;
 
@@ -138,9 +142,10 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const void* phi, const v
 lbm_status lbm_step(lbm_ctx* c, int64_t nsteps);
 
 /* Observables at the current time level (synchronises).  ux, uy, p, T are optional device
- * arrays [ny][nx] of the context's dtype receiving u (Eq. (21)), p (Eq. (23); at wall nodes
- * phi_b p_b = phi_f p_f), T (Eq. (36)).  Returns LBM_E_DIVERGED with o->diverged = 1 when a
- * field is not finite or max |u| exceeds cs. */
+ * arrays [ny][nx] of the context's dtype receiving u (Eq. (21)), the dynamic pressure
+ * p - rho0 cs^2 / phi (p of Eq. (23) less its rest value, which FP32 could not carry the
+ * dynamic part on top of; at wall nodes phi_b p_b = phi_f p_f), T (Eq. (36)).  Returns
+ * LBM_E_DIVERGED with o->diverged = 1 when a field is not finite or max |u| exceeds cs. */
 lbm_status lbm_observables(lbm_ctx* c, lbm_obs* o, void* ux, void* uy, void* p, void* T);
 
 /* Stream function at the current time level (synchronises): psi (device array [ny][nx] of the

@@ -72,10 +72,15 @@ _lib = None
 
 
 def lib():
+    """The oracle library; LBM_REF_LIB names another build of it (the mutation tests load
+    deliberately broken copies of the oracle this way)."""
     global _lib
     if _lib is None:
-        build()
-        L = C.CDLL(LIB)
+        path = os.environ.get("LBM_REF_LIB")
+        if not path:
+            build()
+            path = LIB
+        L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
         L.ref_create.restype = C.c_void_p
         L.ref_create.argtypes = [C.POINTER(RefParams), dp, C.c_double, dp]
@@ -150,6 +155,7 @@ class RefLattice:
         for a in (self._phi, self._K):
             if a is not None and a.shape != (self.ny, self.nx):
                 raise ValueError(f"field shape {a.shape} != {(self.ny, self.nx)}")
+        self._phi_uniform = float(phi_uniform)
         self._h = lib().ref_create(C.byref(self._p), _ptr(self._phi), float(phi_uniform),
                                    _ptr(self._K))
         if not self._h:
@@ -173,11 +179,16 @@ class RefLattice:
     def time(self) -> int:
         return int(lib().ref_get_step(self._h))
 
-    def observables(self) -> dict:
+    def observables(self, dynamic_pressure: bool = False) -> dict:
+        """Fields u_x, u_y, p (Eq. (23)), T (Eq. (36)) and Nu_hot, Nu_cold (Eq. (38)); with
+        ``dynamic_pressure`` p less its rest value rho0 cs^2 / phi (cs^2 = 1/3), node by node."""
         shp = (self.ny, self.nx)
         ux, uy, p, T = (np.empty(shp) for _ in range(4))
         out = np.zeros(5)
         lib().ref_observables(self._h, _ptr(ux), _ptr(uy), _ptr(p), _ptr(T), _ptr(out))
+        if dynamic_pressure:
+            phi = self._phi if self._phi is not None else self._phi_uniform
+            p = p - self.params["rho0"] / 3.0 / phi
         return dict(ux=ux, uy=uy, p=p, T=T, nu_hot=out[0], nu_cold=out[1], max_speed=out[2],
                     mass_err=out[3], diverged=bool(out[4]))
 

@@ -12,11 +12,12 @@ from __future__ import annotations
 import ctypes as C
 
 from . import _abi
-from ._abi import (LBM_FP32, LBM_FP64, LBM_PERIODIC, LBM_WALL_ADIABATIC, LBM_WALL_ISOTHERMAL,
-                   LbmError, LbmObs, LbmParams, check, library, ptr)
+from ._abi import (LBM_FP32, LBM_FP32_F64, LBM_FP64, LBM_PERIODIC, LBM_WALL_ADIABATIC,
+                   LBM_WALL_ISOTHERMAL, LbmError, LbmObs, LbmParams, check, library, ptr)
 
 __all__ = [
-    "LbmParams", "LbmObs", "LbmError", "LBM_FP32", "LBM_FP64", "LBM_WALL_ISOTHERMAL",
+    "LbmParams", "LbmObs", "LbmError", "LBM_FP32", "LBM_FP64", "LBM_FP32_F64",
+    "LBM_WALL_ISOTHERMAL",
     "LBM_WALL_ADIABATIC", "LBM_PERIODIC", "library", "make_params", "params_dict",
     "lbm_default_params", "lbm_derived", "lbm_workspace_size", "lbm_init", "lbm_step",
     "lbm_observables", "lbm_grad", "lbm_stream_function", "lbm_state_size", "lbm_save", "lbm_load", "lbm_destroy",
@@ -159,11 +160,12 @@ def lbm_last_error() -> str:
 # ---- parameters from plain dicts --------------------------------------------------------------
 
 def make_params(**kw) -> LbmParams:
-    """lbm_params from keyword arguments over the paper's defaults; dtype may be 'fp32'/'fp64'."""
+    """lbm_params from keyword arguments over the paper's defaults; dtype may be 'fp32', 'fp64' or
+    'fp32_f64' (FP32 storage, FP64 arithmetic)."""
     p = lbm_default_params()
     for k, v in kw.items():
         if k == "dtype" and isinstance(v, str):
-            v = {"fp32": LBM_FP32, "fp64": LBM_FP64}[v]
+            v = {"fp32": LBM_FP32, "fp64": LBM_FP64, "fp32_f64": LBM_FP32_F64}[v]
         if k in _ARRAY_FIELDS:
             arr = getattr(p, k)
             for i, x in enumerate(v):

@@ -56,6 +56,9 @@ class Cavity:
         return self
 
     def observables(self, fields: bool = True) -> dict:
+        """Nu_hot, Nu_cold (Eq. (38)), max |u|, mass deviation, step, diverged; with
+        ``fields`` also u_x, u_y, the dynamic pressure p - rho0 cs^2 / phi and T as [ny][nx]
+        tensors of the cavity's dtype."""
         if fields:
             ux, uy, p, T = (torch.empty(self.ny, self.nx, dtype=self.dtype, device=self.device)
                             for _ in range(4))

@@ -80,9 +80,12 @@ Derived derive(const lbm_params& p) {
 
 bool walled(const lbm_params& p, int side) { return p.bc[side] != LBM_PERIODIC; }
 
+// Bytes per stored value (populations, medium planes, fields) of a dtype.
+size_t storage_bytes(int dtype) { return dtype == LBM_FP64 ? 8 : 4; }
+
 lbm_status validate(const lbm_params& p) {
-    if (p.dtype != LBM_FP32 && p.dtype != LBM_FP64)
-        return fail(LBM_E_INVAL, "dtype %d is neither LBM_FP32 nor LBM_FP64", p.dtype);
+    if (p.dtype != LBM_FP32 && p.dtype != LBM_FP64 && p.dtype != LBM_FP32_F64)
+        return fail(LBM_E_INVAL, "dtype %d is not LBM_FP32, LBM_FP64 or LBM_FP32_F64", p.dtype);
     for (int s = 0; s < 4; ++s)
         if (p.bc[s] < LBM_WALL_ISOTHERMAL || p.bc[s] > LBM_PERIODIC)
             return fail(LBM_E_INVAL, "bc[%d] = %d is not a side condition", s, p.bc[s]);
@@ -192,7 +195,7 @@ struct Layout {
 
 Layout make_layout(const lbm_params& p, int64_t nsteps_max, bool med_planes) {
     const Geo G = make_geo(p);
-    const size_t esz = p.dtype == LBM_FP64 ? 8 : 4;
+    const size_t esz = storage_bytes(p.dtype);
     Layout L{};
     L.state_bytes = align_up(size_t(kPlanes) * G.plane * esz);
     size_t o = 0;
@@ -266,6 +269,37 @@ struct lbm_ctx {
 
 namespace {
 
+template <class T>
+struct Tag {
+    using type = T;
+};
+
+// Calls f(Tag<S>, Tag<R>) with the storage type S and the arithmetic type R of a dtype.
+template <class F>
+hipError_t with_types(int dtype, F&& f) {
+    if (dtype == LBM_FP64) return f(Tag<double>{}, Tag<double>{});
+    if (dtype == LBM_FP32_F64) return f(Tag<float>{}, Tag<double>{});
+    return f(Tag<float>{}, Tag<float>{});
+}
+
+// Kernel parameters in arithmetic type R: of the context, and of cavity i of a batch.
+template <class R>
+const Phys<R>& phys(const lbm_ctx* c);
+template <>
+const Phys<float>& phys<float>(const lbm_ctx* c) { return c->P32; }
+template <>
+const Phys<double>& phys<double>(const lbm_ctx* c) { return c->P64; }
+template <class R>
+const Phys<R>& bphys(const lbm_ctx* c, int i);
+template <>
+const Phys<float>& bphys<float>(const lbm_ctx* c, int i) { return c->bP32[i]; }
+template <>
+const Phys<double>& bphys<double>(const lbm_ctx* c, int i) { return c->bP64[i]; }
+
+#define LBM_TYPES(st, rt)                  \
+    using S = typename decltype(st)::type; \
+    using R = typename decltype(rt)::type;
+
 lbm_status check_ctx(const lbm_ctx* c, bool want_batch) {
     if (!c) return fail(LBM_E_INVAL, "null context");
     if (c->batch != want_batch)
@@ -274,8 +308,10 @@ lbm_status check_ctx(const lbm_ctx* c, bool want_batch) {
 }
 
 hipError_t step_once(lbm_ctx* c, const void* src, void* dst, hipStream_t s) {
-    if (c->p.dtype == LBM_FP64) return launch_step<double>(src, dst, c->medp(), c->G, c->P64, s);
-    return launch_step<float>(src, dst, c->medp(), c->G, c->P32, s);
+    return with_types(c->p.dtype, [&](auto st, auto rt) {
+        LBM_TYPES(st, rt)
+        return launch_step<S, R>(src, dst, c->medp(), c->G, phys<R>(c), s);
+    });
 }
 
 // Capture kGraphSteps launches (an even count, so the buffers end where they started) into an
@@ -345,7 +381,7 @@ lbm_status batch_layout(int32_t n, const lbm_params* p, BatchLayout* L) {
     if (elems >= (1LL << 31))
         return fail(LBM_E_INVAL, "batch state of %lld elements exceeds 2^31", elems);
     if (tiles >= (size_t(1) << 31)) return fail(LBM_E_INVAL, "too many tiles");
-    const size_t esz = dt == LBM_FP64 ? 8 : 4;
+    const size_t esz = storage_bytes(dt);
     L->state_bytes = align_up(size_t(elems) * esz);
     size_t o = 0;
     L->off_buf[0] = o;
@@ -366,8 +402,7 @@ lbm_status batch_layout(int32_t n, const lbm_params* p, BatchLayout* L) {
 }
 
 hipError_t batch_rest(lbm_ctx* c) {
-    const bool f64 = c->p.dtype == LBM_FP64;
-    const size_t esz = f64 ? 8 : 4;
+    const size_t esz = storage_bytes(c->p.dtype);
     for (int b = 0; b < 2; ++b) {
         char* base = c->ws + c->b_off_buf[b];
         for (int i = 0; i < c->ncav; ++i) {
@@ -376,8 +411,8 @@ hipError_t batch_rest(lbm_ctx* c) {
             const double g0 = (1.0 - p.varpi) / 5.0 * (p.T_init - d.T0);
             const double g1 = (4.0 + p.varpi) / 20.0 * (p.T_init - d.T0);
             void* dst = base + size_t(c->boff[i]) * esz;
-            hipError_t e = f64 ? launch_rest<double>(dst, c->bG[i], g0, g1, c->stream)
-                               : launch_rest<float>(dst, c->bG[i], g0, g1, c->stream);
+            hipError_t e = esz == 8 ? launch_rest<double>(dst, c->bG[i], g0, g1, c->stream)
+                                    : launch_rest<float>(dst, c->bG[i], g0, g1, c->stream);
             if (e != hipSuccess) return e;
         }
     }
@@ -421,11 +456,11 @@ BatchTable<R> batch_table(const lbm_ctx* c) {
 hipError_t batch_step_once(lbm_ctx* c, int from, hipStream_t s) {
     const void* src = c->ws + c->b_off_buf[from];
     void* dst = c->ws + c->b_off_buf[1 - from];
-    if (c->p.dtype == LBM_FP64)
-        return launch_batch_step<double>(src, dst, batch_table<double>(c), c->b_npt, c->b_wg,
-                                         c->b_nwg, s);
-    return launch_batch_step<float>(src, dst, batch_table<float>(c), c->b_npt, c->b_wg,
-                                    c->b_nwg, s);
+    return with_types(c->p.dtype, [&](auto st, auto rt) {
+        LBM_TYPES(st, rt)
+        return launch_batch_step<S, R>(src, dst, batch_table<R>(c), c->b_npt, c->b_wg, c->b_nwg,
+                                       s);
+    });
 }
 
 lbm_status ensure_batch_graph(lbm_ctx* c, int start) {
@@ -477,7 +512,8 @@ std::string batch_key(const lbm_ctx* c) {
     }
     char buf[128];
     snprintf(buf, sizeof buf, "%s|%s|%016llx", arch.c_str(),
-             c->p.dtype == LBM_FP64 ? "fp64" : "fp32", (unsigned long long)h);
+             c->p.dtype == LBM_FP64 ? "fp64" : c->p.dtype == LBM_FP32_F64 ? "fp32_f64" : "fp32",
+             (unsigned long long)h);
     return buf;
 }
 
@@ -691,28 +727,24 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const void* phi, const v
     c->P64 = make_phys<double>(*p, c->d, c->phi_u);
     const double g0 = (1.0 - p->varpi) / 5.0 * (p->T_init - c->d.T0);
     const double g1 = (4.0 + p->varpi) / 20.0 * (p->T_init - c->d.T0);
-    hipError_t e = hipSuccess;
-    const bool f64 = p->dtype == LBM_FP64;
-    if (med) {
-        char* mp = c->ws + L.off_med;
-        const size_t plane_bytes = size_t(c->G.plane) * (f64 ? 8 : 4);
-        const double Kv = std::isinf(c->d.K) ? 1e300 : c->d.K;
-        if (f64) {
-            e = launch_pitch_copy<double>(mp, phi, c->G, phi_uniform, c->stream);
-            if (e == hipSuccess)
-                e = launch_pitch_copy<double>(mp + plane_bytes, K, c->G, Kv, c->stream);
-        } else {
-            e = launch_pitch_copy<float>(mp, phi, c->G, phi_uniform, c->stream);
-            if (e == hipSuccess)
-                e = launch_pitch_copy<float>(mp + plane_bytes, K, c->G, std::isinf(c->d.K) ? 1e30
-                                                                                          : Kv,
-                                             c->stream);
+    hipError_t e = with_types(p->dtype, [&](auto st, auto rt) {
+        LBM_TYPES(st, rt)
+        (void)sizeof(R);
+        hipError_t e1 = hipSuccess;
+        if (med) {
+            char* mp = c->ws + L.off_med;
+            const size_t plane_bytes = size_t(c->G.plane) * sizeof(S);
+            // an infinite K (Da <= 0) is stored as a large finite value: drag ~ 1/K vanishes
+            const double Kv = std::isinf(c->d.K) ? (sizeof(S) == 8 ? 1e300 : 1e30) : c->d.K;
+            e1 = launch_pitch_copy<S>(mp, phi, c->G, phi_uniform, c->stream);
+            if (e1 == hipSuccess)
+                e1 = launch_pitch_copy<S>(mp + plane_bytes, K, c->G, Kv, c->stream);
         }
-    }
-    // both buffers, so that the row padding (never written by a step) is defined too
-    for (int b = 0; b < 2 && e == hipSuccess; ++b)
-        e = f64 ? launch_rest<double>(c->buf(b), c->G, g0, g1, c->stream)
-                : launch_rest<float>(c->buf(b), c->G, g0, g1, c->stream);
+        // both buffers, so that the row padding (never written by a step) is defined too
+        for (int b = 0; b < 2 && e1 == hipSuccess; ++b)
+            e1 = launch_rest<S>(c->buf(b), c->G, g0, g1, c->stream);
+        return e1;
+    });
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         delete c;
@@ -759,11 +791,11 @@ lbm_status lbm_observables(lbm_ctx* c, lbm_obs* o, void* ux, void* uy, void* p, 
     double* part = c->part();
     double* res = part + 3 * kObserveWG;
     const double LdT = c->d.L / c->d.dT;
-    hipError_t e = c->p.dtype == LBM_FP64
-                       ? launch_observe<double>(c->buf(c->cur), c->medp(), c->G, c->P64, ux, uy,
-                                                p, T, part, kObserveWG, LdT, res, c->stream)
-                       : launch_observe<float>(c->buf(c->cur), c->medp(), c->G, c->P32, ux, uy,
-                                               p, T, part, kObserveWG, LdT, res, c->stream);
+    hipError_t e = with_types(c->p.dtype, [&](auto st, auto rt) {
+        LBM_TYPES(st, rt)
+        return launch_observe<S, R>(c->buf(c->cur), c->medp(), c->G, phys<R>(c), ux, uy, p, T,
+                                    part, kObserveWG, LdT, res, c->stream);
+    });
     if (e != hipSuccess) return hip_fail(e, "observables launch");
     double h[5];
     HIP_TRY(hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, c->stream), "readback");
@@ -787,11 +819,11 @@ lbm_status lbm_stream_function(lbm_ctx* c, void* psi) {
     lbm_status s = check_ctx(c, false);
     if (s != LBM_OK) return s;
     if (!psi) return fail(LBM_E_INVAL, "null psi");
-    hipError_t e = c->p.dtype == LBM_FP64
-                       ? launch_stream_function<double>(c->buf(c->cur), c->medp(), c->G, c->P64,
-                                                        psi, c->stream)
-                       : launch_stream_function<float>(c->buf(c->cur), c->medp(), c->G, c->P32,
-                                                       psi, c->stream);
+    hipError_t e = with_types(c->p.dtype, [&](auto st, auto rt) {
+        LBM_TYPES(st, rt)
+        return launch_stream_function<S, R>(c->buf(c->cur), c->medp(), c->G, phys<R>(c), psi,
+                                            c->stream);
+    });
     if (e != hipSuccess) return hip_fail(e, "stream function launch");
     HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
     return LBM_OK;
@@ -846,8 +878,7 @@ lbm_status lbm_grad(lbm_ctx* c, double dJ, void* dJ_dphi, void* dJ_dK) {
     if (c->p.checkpoint_every <= 0)
         return fail(LBM_E_STATE, "no adjoint tape (checkpoint_every = 0)");
     if (!std::isfinite(dJ)) return fail(LBM_E_INVAL, "dJ is not finite");
-    const bool f64 = c->p.dtype == LBM_FP64;
-    const size_t esz = f64 ? 8 : 4;
+    const size_t esz = storage_bytes(c->p.dtype);
     const size_t nel = c->L.state_bytes / esz;
     const int64_t N = c->step;
     const int64_t C = c->p.checkpoint_every;
@@ -855,17 +886,19 @@ lbm_status lbm_grad(lbm_ctx* c, double dJ, void* dJ_dphi, void* dJ_dK) {
     double* gphi = c->gacc(0);
     double* gK = c->gacc(1);
     HIP_TRY(launch_fill_f64(gphi, 2 * size_t(c->G.plane), st), "zero gradients");
-    HIP_TRY(f64 ? launch_fill<double>(c->lam(0), nel, st) : launch_fill<float>(c->lam(0), nel, st),
-            "zero adjoint");
-    HIP_TRY(f64 ? launch_fill<double>(c->lam(1), nel, st) : launch_fill<float>(c->lam(1), nel, st),
-            "zero adjoint");
+    for (int b = 0; b < 2; ++b)
+        HIP_TRY(esz == 8 ? launch_fill<double>(c->lam(b), nel, st)
+                         : launch_fill<float>(c->lam(b), nel, st),
+                "zero adjoint");
     int lc = 0;  // buffer holding the adjoint of the latest state
     if (N > 0) {
         const double LdT = c->d.L / c->d.dT;
-        HIP_TRY(f64 ? launch_adjoint_seed<double>(c->buf(c->cur), c->lam(lc), c->G, c->P64, LdT,
-                                                  st)
-                    : launch_adjoint_seed<float>(c->buf(c->cur), c->lam(lc), c->G, c->P32, LdT,
-                                                 st),
+        HIP_TRY(with_types(c->p.dtype,
+                           [&](auto stt, auto rt) {
+                               LBM_TYPES(stt, rt)
+                               return launch_adjoint_seed<S, R>(c->buf(c->cur), c->lam(lc), c->G,
+                                                                phys<R>(c), LdT, st);
+                           }),
                 "adjoint seed");
         const int64_t nseg = (N + C - 1) / C;
         for (int64_t sg = nseg - 1; sg >= 0; --sg) {
@@ -879,10 +912,13 @@ lbm_status lbm_grad(lbm_ctx* c, double dJ, void* dJ_dphi, void* dJ_dK) {
                         "recompute launch");
             for (int64_t k = len - 1; k >= 0; --k) {
                 const void* X = c->seg(size_t(k));
-                HIP_TRY(f64 ? launch_adjoint_step<double>(X, c->lam(lc), c->lam(1 - lc),
-                                                          c->medp(), gphi, gK, c->G, c->P64, st)
-                            : launch_adjoint_step<float>(X, c->lam(lc), c->lam(1 - lc),
-                                                         c->medp(), gphi, gK, c->G, c->P32, st),
+                HIP_TRY(with_types(c->p.dtype,
+                                   [&](auto stt, auto rt) {
+                                       LBM_TYPES(stt, rt)
+                                       return launch_adjoint_step<S, R>(
+                                           X, c->lam(lc), c->lam(1 - lc), c->medp(), gphi, gK,
+                                           c->G, phys<R>(c), st);
+                                   }),
                         "adjoint step launch");
                 lc = 1 - lc;
             }
@@ -956,8 +992,9 @@ lbm_status lbm_batch_init(lbm_ctx** out, int32_t n, const lbm_params* p,
         c->bP64.push_back(make_phys<double>(p[i], d, phi_uniform[i]));
         c->bLdT.push_back(d.L / d.dT);
     }
-    const bool f64 = p[0].dtype == LBM_FP64;
-    hipError_t e = f64 ? hipMemcpy(c->ws + L.off_phys, c->bP64.data(), n * sizeof(Phys<double>),
+    // the parameter table in the arithmetic type
+    const bool r64 = p[0].dtype != LBM_FP32;
+    hipError_t e = r64 ? hipMemcpy(c->ws + L.off_phys, c->bP64.data(), n * sizeof(Phys<double>),
                                    hipMemcpyHostToDevice)
                        : hipMemcpy(c->ws + L.off_phys, c->bP32.data(), n * sizeof(Phys<float>),
                                    hipMemcpyHostToDevice);
@@ -1009,8 +1046,7 @@ lbm_status lbm_batch_observables(lbm_ctx* c, lbm_obs* o) {
     if (s != LBM_OK) return s;
     if (!o) return fail(LBM_E_INVAL, "null lbm_obs");
     const int n = c->ncav;
-    const bool f64 = c->p.dtype == LBM_FP64;
-    const size_t esz = f64 ? 8 : 4;
+    const size_t esz = storage_bytes(c->p.dtype);
     double* part0 = (double*)(c->ws + c->b_off_part);
     const size_t per = 3 * kBatchObsWG + 8;
     char* base = c->ws + c->b_off_buf[c->cur];
@@ -1018,13 +1054,12 @@ lbm_status lbm_batch_observables(lbm_ctx* c, lbm_obs* o) {
         const void* src = base + size_t(c->boff[i]) * esz;
         double* part = part0 + i * per;
         double* res = part + 3 * kBatchObsWG;
-        hipError_t e =
-            f64 ? launch_observe<double>(src, nullptr, c->bG[i], c->bP64[i], nullptr, nullptr,
-                                         nullptr, nullptr, part, kBatchObsWG, c->bLdT[i], res,
-                                         c->stream)
-                : launch_observe<float>(src, nullptr, c->bG[i], c->bP32[i], nullptr, nullptr,
+        hipError_t e = with_types(c->p.dtype, [&](auto st, auto rt) {
+            LBM_TYPES(st, rt)
+            return launch_observe<S, R>(src, nullptr, c->bG[i], bphys<R>(c, i), nullptr, nullptr,
                                         nullptr, nullptr, part, kBatchObsWG, c->bLdT[i], res,
                                         c->stream);
+        });
         if (e != hipSuccess) return hip_fail(e, "batch observables launch");
     }
     std::vector<double> h(size_t(n) * per);
@@ -1055,15 +1090,15 @@ lbm_status lbm_batch_fields(lbm_ctx* c, int32_t i, void* ux, void* uy, void* p, 
     lbm_status s = check_ctx(c, true);
     if (s != LBM_OK) return s;
     if (i < 0 || i >= c->ncav) return fail(LBM_E_INVAL, "cavity %d of %d", i, c->ncav);
-    const bool f64 = c->p.dtype == LBM_FP64;
-    const size_t esz = f64 ? 8 : 4;
+    const size_t esz = storage_bytes(c->p.dtype);
     const void* src = c->ws + c->b_off_buf[c->cur] + size_t(c->boff[i]) * esz;
     double* part = (double*)(c->ws + c->b_off_part) + size_t(i) * (3 * kBatchObsWG + 8);
     double* res = part + 3 * kBatchObsWG;
-    hipError_t e = f64 ? launch_observe<double>(src, nullptr, c->bG[i], c->bP64[i], ux, uy, p, T,
-                                                part, kBatchObsWG, c->bLdT[i], res, c->stream)
-                       : launch_observe<float>(src, nullptr, c->bG[i], c->bP32[i], ux, uy, p, T,
-                                               part, kBatchObsWG, c->bLdT[i], res, c->stream);
+    hipError_t e = with_types(c->p.dtype, [&](auto st, auto rt) {
+        LBM_TYPES(st, rt)
+        return launch_observe<S, R>(src, nullptr, c->bG[i], bphys<R>(c, i), ux, uy, p, T, part,
+                                    kBatchObsWG, c->bLdT[i], res, c->stream);
+    });
     if (e != hipSuccess) return hip_fail(e, "batch fields launch");
     HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
     return LBM_OK;

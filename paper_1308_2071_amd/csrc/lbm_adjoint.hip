@@ -128,7 +128,7 @@ __device__ __forceinline__ void macros_vjp(const R f[9], const R g[5], R phi, R 
     const R q = sqrt(l0 * l0 + l1 * vm);
     const R den = l0 + q;
     const R inv_den = R(1) / den;
-    const R ux = vx * inv_den, uy = vy * inv_den;
+    const R ux = vx / den, uy = vy / den;     // as the forward step computes them
     const R uu = ux * ux + uy * uy;
     const R um = sqrt(uu);
     const R drag = md.c_lin + md.c_nl * um;
@@ -266,11 +266,12 @@ __device__ __forceinline__ void wall_collide_vjp(const R fb[9], const R gb[5], R
 
 // One backward step.  state: the forward state X^n (post-collision populations entering step
 // n); lam_in: adjoint of X^{n+1}; lam_out: adjoint of X^n (written); gphi, gK: FP64 gradient
-// planes [ny][pitch] accumulated in place.
-template <typename R, bool PN>
+// planes [ny][pitch] accumulated in place.  S: storage type of state, adjoint and medium;
+// R: arithmetic type.
+template <typename S, typename R, bool PN>
 __global__ __launch_bounds__(256) void adjoint_step_kernel(
-    const R* __restrict__ state, const R* __restrict__ lam_in, R* __restrict__ lam_out,
-    const R* __restrict__ med, double* __restrict__ gphi, double* __restrict__ gK, Geo G,
+    const S* __restrict__ state, const S* __restrict__ lam_in, S* __restrict__ lam_out,
+    const S* __restrict__ med, double* __restrict__ gphi, double* __restrict__ gK, Geo G,
     Phys<R> P, int tiles_x) {
     const int t = blockIdx.x;
     const int y = t / tiles_x;
@@ -294,18 +295,18 @@ __global__ __launch_bounds__(256) void adjoint_step_kernel(
         // own slots are not read in the forward step
 #pragma unroll
         for (int i = 0; i < 9; ++i)
-            if (ok[i]) lam_out[i * G.plane + sy[i] * G.pitch + sx[i]] = R(0);
+            if (ok[i]) lam_out[i * G.plane + sy[i] * G.pitch + sx[i]] = S(0);
 #pragma unroll
         for (int i = 0; i < 5; ++i)
-            if (ok[i]) lam_out[(9 + i) * G.plane + sy[i] * G.pitch + sx[i]] = R(0);
+            if (ok[i]) lam_out[(9 + i) * G.plane + sy[i] * G.pitch + sx[i]] = S(0);
         // d/dphi_b through F_b = phi_b G_b
         R f[9], g[5];
         Mac<R> m;
         Med<R> md;
-        node_state<R, PN>(state, med, G, P, x, y, f, g, m, md);
+        node_state<R, PN, S>(state, med, G, P, x, y, f, g, m, md);
         R lout[14];
 #pragma unroll
-        for (int i = 0; i < 14; ++i) lout[i] = lam_in[i * G.plane + o];
+        for (int i = 0; i < 14; ++i) lout[i] = R(lam_in[i * G.plane + o]);
         R lfb[9], lgb[5], lth, lphib, lPb;
         wall_collide_vjp<R>(f, g, m.theta, m.P, md.phi, P, lout, lfb, lgb, lth, lphib, lPb);
         gphi[o] += double(lphib);
@@ -314,11 +315,11 @@ __global__ __launch_bounds__(256) void adjoint_step_kernel(
 
     // fluid node: forward recompute
     R f[9], g[5];
-    pull<R>(state, G, x, y, f, g);
+    pull<R, S>(state, G, x, y, f, g);
     R phi, K;
     if constexpr (PN) {
-        phi = med[o];
-        K = med[G.plane + o];
+        phi = R(med[o]);
+        K = R(med[G.plane + o]);
     } else {
         phi = P.phi;
         K = P.c_lin > R(0) ? phi * P.nu / P.c_lin : R(INFINITY);
@@ -329,7 +330,7 @@ __global__ __launch_bounds__(256) void adjoint_step_kernel(
     const Mac<R> m = fluid_macros<R>(f, g, mdu, P);
     R lout[14];
 #pragma unroll
-    for (int i = 0; i < 14; ++i) lout[i] = lam_in[i * G.plane + o];
+    for (int i = 0; i < 14; ++i) lout[i] = R(lam_in[i * G.plane + o]);
     R af[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, ag[5] = {0, 0, 0, 0, 0};
     MacAdj<R> A{};
     collide_vjp<R>(f, g, m, mdu, P, lout, lout + 9, af, ag, A);
@@ -363,8 +364,8 @@ __global__ __launch_bounds__(256) void adjoint_step_kernel(
             const int ob = yb * G.pitch + xb;
             R lb[14];
 #pragma unroll
-            for (int i = 0; i < 14; ++i) lb[i] = lam_in[i * G.plane + ob];
-            const R phi_b = PN ? med[ob] : P.phi;
+            for (int i = 0; i < 14; ++i) lb[i] = R(lam_in[i * G.plane + ob]);
+            const R phi_b = PN ? R(med[ob]) : P.phi;
             R lfb[9], lgb[5], lthb, lphib, lPb;
             wall_collide_vjp<R>(fb, gb, theta_b, m.P, phi_b, P, lb, lfb, lgb, lthb, lphib, lPb);
             (void)lphib;  // accumulated by the wall node's own thread
@@ -376,9 +377,9 @@ __global__ __launch_bounds__(256) void adjoint_step_kernel(
     }
     macros_vjp<R>(f, g, phi, K, mdu, P, A, af, ag, lphi, lK);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) lam_out[i * G.plane + sy[i] * G.pitch + sx[i]] = af[i];
+    for (int i = 0; i < 9; ++i) lam_out[i * G.plane + sy[i] * G.pitch + sx[i]] = S(af[i]);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) lam_out[(9 + i) * G.plane + sy[i] * G.pitch + sx[i]] = ag[i];
+    for (int i = 0; i < 5; ++i) lam_out[(9 + i) * G.plane + sy[i] * G.pitch + sx[i]] = S(ag[i]);
     gphi[o] += double(lphi);
     gK[o] += double(lK);
 }
@@ -394,8 +395,8 @@ __device__ __forceinline__ double nu_weight(const Geo& G, int x, int y, double s
     return scale * w * c[x] / 12.0;
 }
 
-template <typename R>
-__global__ void adjoint_seed_kernel(R* __restrict__ lam, Geo G, Phys<R> P, double scale) {
+template <typename S, typename R>
+__global__ void adjoint_seed_kernel(S* __restrict__ lam, Geo G, Phys<R> P, double scale) {
     const int ncol = G.nx < 6 ? G.nx : 6;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= ncol * G.ny) return;
@@ -424,7 +425,7 @@ __global__ void adjoint_seed_kernel(R* __restrict__ lam, Geo G, Phys<R> P, doubl
     const int sx[5] = {x, xm, x, xp, x};
     const int sy[5] = {y, y, ym, y, yp};
 #pragma unroll
-    for (int i = 0; i < 5; ++i) lam[(9 + i) * G.plane + sy[i] * G.pitch + sx[i]] = R(c);
+    for (int i = 0; i < 5; ++i) lam[(9 + i) * G.plane + sy[i] * G.pitch + sx[i]] = S(c);
 }
 
 template <typename R>
@@ -443,31 +444,31 @@ __global__ void unpitch_scale_kernel(double* __restrict__ dst, const double* __r
     }
 }
 
-template <typename R>
+template <typename S, typename R>
 hipError_t launch_adjoint_seed(const void* state, void* lam, const Geo& G, const Phys<R>& P,
                                double L_over_dT, hipStream_t s) {
     (void)state;
     const int ncol = G.nx < 6 ? G.nx : 6;
     const int n = ncol * G.ny;
     const double scale = -L_over_dT / double(G.ny - 1);
-    adjoint_seed_kernel<R><<<(n + 255) / 256, 256, 0, s>>>((R*)lam, G, P, scale);
+    adjoint_seed_kernel<S, R><<<(n + 255) / 256, 256, 0, s>>>((S*)lam, G, P, scale);
     return hipGetLastError();
 }
 
-template <typename R>
+template <typename S, typename R>
 hipError_t launch_adjoint_step(const void* state, const void* lam_in, void* lam_out,
                                const void* med, double* gphi, double* gK, const Geo& G,
                                const Phys<R>& P, hipStream_t s) {
     const int tiles_x = (G.nx + 255) / 256;
     const int nwg = tiles_x * G.ny;
     if (med)
-        adjoint_step_kernel<R, true><<<nwg, 256, 0, s>>>((const R*)state, (const R*)lam_in,
-                                                         (R*)lam_out, (const R*)med, gphi, gK,
-                                                         G, P, tiles_x);
+        adjoint_step_kernel<S, R, true><<<nwg, 256, 0, s>>>((const S*)state, (const S*)lam_in,
+                                                            (S*)lam_out, (const S*)med, gphi, gK,
+                                                            G, P, tiles_x);
     else
-        adjoint_step_kernel<R, false><<<nwg, 256, 0, s>>>((const R*)state, (const R*)lam_in,
-                                                          (R*)lam_out, nullptr, gphi, gK, G, P,
-                                                          tiles_x);
+        adjoint_step_kernel<S, R, false><<<nwg, 256, 0, s>>>((const S*)state, (const S*)lam_in,
+                                                             (S*)lam_out, nullptr, gphi, gK, G,
+                                                             P, tiles_x);
     return hipGetLastError();
 }
 
@@ -488,16 +489,16 @@ hipError_t launch_unpitch_scale(double* dst, const double* src, const Geo& G, do
     return hipGetLastError();
 }
 
-template hipError_t launch_adjoint_seed<float>(const void*, void*, const Geo&,
-                                               const Phys<float>&, double, hipStream_t);
-template hipError_t launch_adjoint_seed<double>(const void*, void*, const Geo&,
-                                                const Phys<double>&, double, hipStream_t);
-template hipError_t launch_adjoint_step<float>(const void*, const void*, void*, const void*,
-                                               double*, double*, const Geo&, const Phys<float>&,
-                                               hipStream_t);
-template hipError_t launch_adjoint_step<double>(const void*, const void*, void*, const void*,
-                                                double*, double*, const Geo&,
-                                                const Phys<double>&, hipStream_t);
+#define LBM_ADJ_INSTANCES(S, R)                                                                  \
+    template hipError_t launch_adjoint_seed<S, R>(const void*, void*, const Geo&,                \
+                                                  const Phys<R>&, double, hipStream_t);          \
+    template hipError_t launch_adjoint_step<S, R>(const void*, const void*, void*, const void*,  \
+                                                  double*, double*, const Geo&, const Phys<R>&,  \
+                                                  hipStream_t);
+LBM_ADJ_INSTANCES(float, float)
+LBM_ADJ_INSTANCES(double, double)
+LBM_ADJ_INSTANCES(float, double)
+#undef LBM_ADJ_INSTANCES
 template hipError_t launch_fill<float>(void*, size_t, hipStream_t);
 template hipError_t launch_fill<double>(void*, size_t, hipStream_t);
 

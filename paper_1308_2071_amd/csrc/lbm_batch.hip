@@ -15,9 +15,10 @@ namespace lbm {
 // wavefront per row), so narrow cavities still fill every wavefront.  CHUNKED: each
 // work-group walks one contiguous run of the tile queue (consecutive tiles mostly share a
 // cavity, so its parameters stay in the scalar cache); otherwise one tile per work-group.
-template <typename R, int TH, int NPT, bool CHUNKED>
-__global__ __launch_bounds__(64 * TH) void batch_step_kernel(const R* __restrict__ src,
-                                                             R* __restrict__ dst,
+// S: storage type, R: arithmetic type.
+template <typename S, typename R, int TH, int NPT, bool CHUNKED>
+__global__ __launch_bounds__(64 * TH) void batch_step_kernel(const S* __restrict__ src,
+                                                             S* __restrict__ dst,
                                                              const BatchCavity* __restrict__ cav,
                                                              const Phys<R>* __restrict__ phys,
                                                              const int* __restrict__ tile_cav,
@@ -40,8 +41,8 @@ __global__ __launch_bounds__(64 * TH) void batch_step_kernel(const R* __restrict
         const int y = ty * TH + wave;
         if (y >= C.G.ny) continue;
         const int x0 = (lt - ty * C.tiles_x) * (64 * NPT) + lane;
-        const R* s = src + C.off;
-        R* d = dst + C.off;
+        const S* s = src + C.off;
+        S* d = dst + C.off;
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
             const int x = x0 + k * 64;
@@ -49,55 +50,60 @@ __global__ __launch_bounds__(64 * TH) void batch_step_kernel(const R* __restrict
                 R f[9], g[5];
                 Mac<R> m;
                 Med<R> md;
-                node_state<R, false>(s, nullptr, C.G, P, x, y, f, g, m, md);
+                node_state<R, false, S>(s, nullptr, C.G, P, x, y, f, g, m, md);
                 collide<R>(f, g, m, md, P);
                 const int o = y * C.G.pitch + x;
 #pragma unroll
-                for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(f[i], d + i * C.G.plane + o);
+                for (int i = 0; i < 9; ++i)
+                    __builtin_nontemporal_store(S(f[i]), d + i * C.G.plane + o);
 #pragma unroll
                 for (int i = 0; i < 5; ++i)
-                    __builtin_nontemporal_store(g[i], d + (9 + i) * C.G.plane + o);
+                    __builtin_nontemporal_store(S(g[i]), d + (9 + i) * C.G.plane + o);
             }
         }
     }
 }
 
-template <typename R, int TH, int NPT>
+template <typename S, typename R, int TH, int NPT>
 static hipError_t launch_v(const void* src, void* dst, const BatchTable<R>& T, int nwg,
                            hipStream_t s) {
     if (nwg >= T.ntiles)
-        batch_step_kernel<R, TH, NPT, false><<<T.ntiles, 64 * TH, 0, s>>>(
-            (const R*)src, (R*)dst, T.cav, T.phys, T.tile_cav, T.ntiles);
+        batch_step_kernel<S, R, TH, NPT, false><<<T.ntiles, 64 * TH, 0, s>>>(
+            (const S*)src, (S*)dst, T.cav, T.phys, T.tile_cav, T.ntiles);
     else
-        batch_step_kernel<R, TH, NPT, true><<<nwg, 64 * TH, 0, s>>>(
-            (const R*)src, (R*)dst, T.cav, T.phys, T.tile_cav, T.ntiles);
+        batch_step_kernel<S, R, TH, NPT, true><<<nwg, 64 * TH, 0, s>>>(
+            (const S*)src, (S*)dst, T.cav, T.phys, T.tile_cav, T.ntiles);
     return hipGetLastError();
 }
 
 // Supported tile shapes: rows per work-group (work-group = 64 * rows work-items) and 64-node
 // segments per work-item along x; nwg >= ntiles launches one tile per work-group, fewer runs
 // the chunked persistent form.
-template <typename R>
+template <typename S, typename R>
 hipError_t launch_batch_step(const void* src, void* dst, const BatchTable<R>& T, int nodes_x,
                              int rows, int nwg, hipStream_t s) {
     switch (rows * 8 + nodes_x) {
-        case 1 * 8 + 1: return launch_v<R, 1, 1>(src, dst, T, nwg, s);
-        case 1 * 8 + 2: return launch_v<R, 1, 2>(src, dst, T, nwg, s);
-        case 1 * 8 + 4: return launch_v<R, 1, 4>(src, dst, T, nwg, s);
-        case 2 * 8 + 1: return launch_v<R, 2, 1>(src, dst, T, nwg, s);
-        case 2 * 8 + 2: return launch_v<R, 2, 2>(src, dst, T, nwg, s);
-        case 2 * 8 + 4: return launch_v<R, 2, 4>(src, dst, T, nwg, s);
-        case 4 * 8 + 1: return launch_v<R, 4, 1>(src, dst, T, nwg, s);
-        case 4 * 8 + 2: return launch_v<R, 4, 2>(src, dst, T, nwg, s);
-        case 4 * 8 + 4: return launch_v<R, 4, 4>(src, dst, T, nwg, s);
-        case 8 * 8 + 1: return launch_v<R, 8, 1>(src, dst, T, nwg, s);
+        case 1 * 8 + 1: return launch_v<S, R, 1, 1>(src, dst, T, nwg, s);
+        case 1 * 8 + 2: return launch_v<S, R, 1, 2>(src, dst, T, nwg, s);
+        case 1 * 8 + 4: return launch_v<S, R, 1, 4>(src, dst, T, nwg, s);
+        case 2 * 8 + 1: return launch_v<S, R, 2, 1>(src, dst, T, nwg, s);
+        case 2 * 8 + 2: return launch_v<S, R, 2, 2>(src, dst, T, nwg, s);
+        case 2 * 8 + 4: return launch_v<S, R, 2, 4>(src, dst, T, nwg, s);
+        case 4 * 8 + 1: return launch_v<S, R, 4, 1>(src, dst, T, nwg, s);
+        case 4 * 8 + 2: return launch_v<S, R, 4, 2>(src, dst, T, nwg, s);
+        case 4 * 8 + 4: return launch_v<S, R, 4, 4>(src, dst, T, nwg, s);
+        case 8 * 8 + 1: return launch_v<S, R, 8, 1>(src, dst, T, nwg, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-template hipError_t launch_batch_step<float>(const void*, void*, const BatchTable<float>&, int,
-                                             int, int, hipStream_t);
-template hipError_t launch_batch_step<double>(const void*, void*, const BatchTable<double>&, int,
-                                              int, int, hipStream_t);
+template hipError_t launch_batch_step<float, float>(const void*, void*, const BatchTable<float>&,
+                                                    int, int, int, hipStream_t);
+template hipError_t launch_batch_step<double, double>(const void*, void*,
+                                                      const BatchTable<double>&, int, int, int,
+                                                      hipStream_t);
+template hipError_t launch_batch_step<float, double>(const void*, void*,
+                                                     const BatchTable<double>&, int, int, int,
+                                                     hipStream_t);
 
 }  // namespace lbm

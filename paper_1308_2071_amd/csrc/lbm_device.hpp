@@ -10,6 +10,11 @@
 // pressure enters through P = phi p - rho0 cs^2.
 //
 // Layout: 14 planes [f0..f8, g0..g4], each [ny][pitch] with x fastest.
+//
+// Precision: S is the storage type of the populations and the medium planes, R the type the
+// arithmetic runs in.  (S, R) = (float, float), (double, double), or (float, double): FP32
+// storage with FP64 arithmetic, where each stored deviation is rounded once per step and none
+// of the ~300 operations in between are.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -74,11 +79,11 @@ __device__ __forceinline__ Med<R> medium_from(R phi, R K, const Phys<R>& P) {
     return m;
 }
 
-template <typename R, bool PN>
-__device__ __forceinline__ Med<R> load_medium(const R* __restrict__ med, int idx, int plane,
+template <typename R, bool PN, typename S = R>
+__device__ __forceinline__ Med<R> load_medium(const S* __restrict__ med, int idx, int plane,
                                               const Phys<R>& P) {
     if constexpr (PN) {
-        return medium_from<R>(med[idx], med[plane + idx], P);
+        return medium_from<R>(R(med[idx]), R(med[plane + idx]), P);
     } else {
         return Med<R>{P.phi, P.inv_phi, P.c_lin, P.c_nl};
     }
@@ -87,8 +92,8 @@ __device__ __forceinline__ Med<R> load_medium(const R* __restrict__ med, int idx
 // Streaming, Eqs. (18) and (35), as a pull: the population i arriving at (x, y) left
 // (x - ex_i, y - ey_i) after the previous collision.  Indices wrap, which is only ever used on
 // periodic axes: on a walled axis the node is interior, so x-1 and x+1 stay in range.
-template <typename R>
-__device__ __forceinline__ void pull(const R* __restrict__ src, const Geo& G, int x, int y,
+template <typename R, typename S = R>
+__device__ __forceinline__ void pull(const S* __restrict__ src, const Geo& G, int x, int y,
                                      R f[9], R g[5]) {
     const int xm = (x == 0) ? G.nx - 1 : x - 1;
     const int xp = (x == G.nx - 1) ? 0 : x + 1;
@@ -96,20 +101,20 @@ __device__ __forceinline__ void pull(const R* __restrict__ src, const Geo& G, in
     const int rp = ((y == G.ny - 1) ? 0 : y + 1) * G.pitch;
     const int r0 = y * G.pitch;
     const int P = G.plane;
-    f[0] = src[0 * P + r0 + x];
-    f[1] = src[1 * P + r0 + xm];
-    f[2] = src[2 * P + rm + x];
-    f[3] = src[3 * P + r0 + xp];
-    f[4] = src[4 * P + rp + x];
-    f[5] = src[5 * P + rm + xm];
-    f[6] = src[6 * P + rm + xp];
-    f[7] = src[7 * P + rp + xp];
-    f[8] = src[8 * P + rp + xm];
-    g[0] = src[9 * P + r0 + x];
-    g[1] = src[10 * P + r0 + xm];
-    g[2] = src[11 * P + rm + x];
-    g[3] = src[12 * P + r0 + xp];
-    g[4] = src[13 * P + rp + x];
+    f[0] = R(src[0 * P + r0 + x]);
+    f[1] = R(src[1 * P + r0 + xm]);
+    f[2] = R(src[2 * P + rm + x]);
+    f[3] = R(src[3 * P + r0 + xp]);
+    f[4] = R(src[4 * P + rp + x]);
+    f[5] = R(src[5 * P + rm + xm]);
+    f[6] = R(src[6 * P + rm + xp]);
+    f[7] = R(src[7 * P + rp + xp]);
+    f[8] = R(src[8 * P + rp + xm]);
+    g[0] = R(src[9 * P + r0 + x]);
+    g[1] = R(src[10 * P + r0 + xm]);
+    g[2] = R(src[11 * P + rm + x]);
+    g[3] = R(src[12 * P + r0 + xp]);
+    g[4] = R(src[13 * P + rp + x]);
 }
 
 // Eqs. (36), (22), (21), (23), (4) at a fluid node, on deviation populations.
@@ -128,8 +133,11 @@ __device__ __forceinline__ Mac<R> fluid_macros(const R f[9], const R g[5], const
     const R l0 = R(0.5) + R(0.25) * md.c_lin;
     const R l1 = R(0.5) * md.c_nl;
     const R vmag = sqrt(vx * vx + vy * vy);
-    const R inv_den = R(1) / (l0 + sqrt(l0 * l0 + l1 * vmag));
-    const R ux = vx * inv_den, uy = vy * inv_den;
+    // divide rather than multiply by a rounded reciprocal: in a uniform medium the denominator
+    // is nearly the same at every node, so the reciprocal's rounding would act as one common
+    // gain on the momentum, step after step
+    const R den = l0 + sqrt(l0 * l0 + l1 * vmag);
+    const R ux = vx / den, uy = vy / den;
     const R uu = ux * ux + uy * uy;
     const R sum18 = ((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8]));
     // phi p = cs^2/(1 - w0) [sum_{i>=1} f_i + rho0 s0(u)], s0 = -w0 |u|^2 / (2 phi cs^2)
@@ -178,6 +186,17 @@ __device__ __forceinline__ void nee_wall(R f[9], R g[5], const Mac<R>& mf, const
     g[4] += P.wt1 * dth + k * uy;
 }
 
+// x / d for a small integer d, correctly rounded: the product with r = RN(1/d) is within one
+// ulp of x/d, the residual x - q d is exact with a fused multiply-add, and one more fused step
+// q + (x - q d) r rounds to RN(x/d) (Markstein, IBM J. Res. Dev. 34 (1990)).  A bare product
+// x r would carry the relative error of r, the same sign at every node and step.
+template <typename R>
+__device__ __forceinline__ R div_const(R x, R d, R r) {
+    const R q = x * r;
+    const R e = fma(-q, d, x);
+    return fma(e, r, q);
+}
+
 // Collision in moment space, Eq. (17) with s0 = s3 = s5 = 1 (Sec. 4) and Eq. (34) with
 // zeta0 = 1 and the heat source of Eq. (30); f, g hold post-streaming deviations on entry and
 // post-collision deviations on exit.
@@ -207,13 +226,15 @@ __device__ __forceinline__ void collide(R f[9], R g[5], const Mac<R>& m, const M
     const R S7 = R(2) * rip * (ux * m.Fx - uy * m.Fy);
     const R S8 = rip * (ux * m.Fy + uy * m.Fx);
     const R rFx = r0 * m.Fx, rFy = r0 * m.Fy;
-    // relaxation, then scaling by 1/|row|^2 for M^-1 = M^T diag(1/|row|^2)
-    const R a1 = (m1 - P.s_e * (m1 - e_eq) + P.os_e * S1) * R(1.0 / 36.0);
-    const R a2 = (m2 - P.s_eps * (m2 - eps_eq) - P.os_eps * S1) * R(1.0 / 36.0);
-    const R a3 = (r0 * ux + R(0.5) * rFx) * R(1.0 / 6.0);
-    const R a4 = (m4 - P.s_q * (m4 + r0 * ux) - P.os_q * rFx) * R(1.0 / 12.0);
-    const R a5 = (r0 * uy + R(0.5) * rFy) * R(1.0 / 6.0);
-    const R a6 = (m6 - P.s_q * (m6 + r0 * uy) - P.os_q * rFy) * R(1.0 / 12.0);
+    // relaxation, then division by |row|^2 for M^-1 = M^T diag(1/|row|^2); the divisions by
+    // 36, 6 and 12 are correctly rounded (not products with the rounded reciprocal, whose
+    // error is one common gain on energy and momentum that accumulates step after step)
+    const R a1 = div_const(m1 - P.s_e * (m1 - e_eq) + P.os_e * S1, R(36), R(1.0 / 36.0));
+    const R a2 = div_const(m2 - P.s_eps * (m2 - eps_eq) - P.os_eps * S1, R(36), R(1.0 / 36.0));
+    const R a3 = div_const(r0 * ux + R(0.5) * rFx, R(6), R(1.0 / 6.0));
+    const R a4 = div_const(m4 - P.s_q * (m4 + r0 * ux) - P.os_q * rFx, R(12), R(1.0 / 12.0));
+    const R a5 = div_const(r0 * uy + R(0.5) * rFy, R(6), R(1.0 / 6.0));
+    const R a6 = div_const(m6 - P.s_q * (m6 + r0 * uy) - P.os_q * rFy, R(12), R(1.0 / 12.0));
     const R a7 = (m7 - P.s_v * (m7 - pxx_eq) + P.os_v * S7) * R(0.25);
     const R a8 = (m8 - P.s_v * (m8 - pxy_eq) + P.os_v * S8) * R(0.25);
     // f' = M^T a (columns of Eq. (11)); a0 = 0 because the post-collision m0' is 0
@@ -237,10 +258,10 @@ __device__ __forceinline__ void collide(R f[9], R g[5], const Mac<R>& m, const M
     const R n2 = g[2] - g[4];
     const R n3 = (g[1] + g[2]) + (g[3] + g[4]) - R(4) * g[0];
     const R n4 = (g[1] - g[2]) + (g[3] - g[4]);
-    const R b0 = (m.theta + P.hQs) * R(0.2);
+    const R b0 = div_const(m.theta + P.hQs, R(5), R(1.0 / 5.0));
     const R b1 = (n1 - P.z_T * (n1 - ux * T * P.inv_sigma)) * R(0.5);
     const R b2 = (n2 - P.z_T * (n2 - uy * T * P.inv_sigma)) * R(0.5);
-    const R b3 = (n3 - P.z3 * (n3 - P.varpi * m.theta) + P.psi3) * R(0.05);
+    const R b3 = div_const(n3 - P.z3 * (n3 - P.varpi * m.theta) + P.psi3, R(20), R(1.0 / 20.0));
     const R b4 = (n4 - P.z4 * n4) * R(0.25);
     // g' = N^T b (columns of Eq. (28))
     g[0] = b0 - R(4) * b3;
@@ -269,8 +290,8 @@ __device__ __forceinline__ R wall_theta(bool onW, bool onE, bool onS, bool onN, 
 
 // Post-streaming, post-wall-reconstruction state of node (x, y): populations, macroscopics and
 // medium.  Wall nodes gather around their inward neighbour (the diagonal one at corners).
-template <typename R, bool PN>
-__device__ __forceinline__ void node_state(const R* __restrict__ src, const R* __restrict__ med,
+template <typename R, bool PN, typename S = R>
+__device__ __forceinline__ void node_state(const S* __restrict__ src, const S* __restrict__ med,
                                            const Geo& G, const Phys<R>& P, int x, int y, R f[9],
                                            R g[5], Mac<R>& m, Med<R>& md) {
     const bool onW = G.wallW && x == 0;
@@ -278,19 +299,19 @@ __device__ __forceinline__ void node_state(const R* __restrict__ src, const R* _
     const bool onS = G.wallS && y == 0;
     const bool onN = G.wallN && y == G.ny - 1;
     if (!(onW || onE || onS || onN)) {
-        pull<R>(src, G, x, y, f, g);
-        md = load_medium<R, PN>(med, y * G.pitch + x, G.plane, P);
+        pull<R, S>(src, G, x, y, f, g);
+        md = load_medium<R, PN, S>(med, y * G.pitch + x, G.plane, P);
         m = fluid_macros<R>(f, g, md, P);
         return;
     }
     const int xf = x + (onW ? 1 : 0) - (onE ? 1 : 0);
     const int yf = y + (onS ? 1 : 0) - (onN ? 1 : 0);
-    pull<R>(src, G, xf, yf, f, g);
-    const Med<R> mdf = load_medium<R, PN>(med, yf * G.pitch + xf, G.plane, P);
+    pull<R, S>(src, G, xf, yf, f, g);
+    const Med<R> mdf = load_medium<R, PN, S>(med, yf * G.pitch + xf, G.plane, P);
     const Mac<R> mf = fluid_macros<R>(f, g, mdf, P);
     const R theta_b = wall_theta<R>(onW, onE, onS, onN, mf.theta, P);
     nee_wall<R>(f, g, mf, mdf, theta_b, P);
-    md = load_medium<R, PN>(med, y * G.pitch + x, G.plane, P);
+    md = load_medium<R, PN, S>(med, y * G.pitch + x, G.plane, P);
     m.theta = theta_b;
     m.ux = R(0);
     m.uy = R(0);

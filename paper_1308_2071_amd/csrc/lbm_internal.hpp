@@ -11,14 +11,17 @@ constexpr int kTileX = 256;      // nodes (work-items) per work-group of the ste
 constexpr int kObserveWG = 512;  // work-groups of the observables pass
 constexpr int kPitchAlign = 64;  // row pitch in elements
 
-template <typename R>
+// Launchers take S, the storage type of populations and medium planes, and R, the arithmetic
+// type; instantiated for (float, float), (double, double) and (float, double).
+
+template <typename S, typename R>
 hipError_t launch_step(const void* src, void* dst, const void* med, const Geo& G,
                        const Phys<R>& P, hipStream_t s);
-template <typename R>
+template <typename S, typename R>
 hipError_t launch_observe(const void* src, const void* med, const Geo& G, const Phys<R>& P,
                           void* ux, void* uy, void* p, void* T, double* part, int nparts,
                           double L_over_dT, double* out, hipStream_t s);
-template <typename R>
+template <typename S, typename R>
 hipError_t launch_stream_function(const void* src, const void* med, const Geo& G,
                                   const Phys<R>& P, void* psi, hipStream_t s);
 template <typename R>
@@ -27,10 +30,10 @@ template <typename R>
 hipError_t launch_pitch_copy(void* dst, const void* src, const Geo& G, double v, hipStream_t s);
 
 // Adjoint (lbm_adjoint.hip)
-template <typename R>
+template <typename S, typename R>
 hipError_t launch_adjoint_seed(const void* state, void* lam, const Geo& G, const Phys<R>& P,
                                double L_over_dT, hipStream_t s);
-template <typename R>
+template <typename S, typename R>
 hipError_t launch_adjoint_step(const void* state, const void* lam_in, void* lam_out,
                                const void* med, double* gphi, double* gK, const Geo& G,
                                const Phys<R>& P, hipStream_t s);
@@ -59,7 +62,7 @@ struct BatchTable {
 
 // rows: rows per tile (work-group = 64 * rows work-items); nodes_x: 64-node segments per
 // work-item along x; nwg >= ntiles: one tile per work-group, else chunked persistent.
-template <typename R>
+template <typename S, typename R>
 hipError_t launch_batch_step(const void* src, void* dst, const BatchTable<R>& T, int nodes_x,
                              int rows, int nwg, hipStream_t s);
 

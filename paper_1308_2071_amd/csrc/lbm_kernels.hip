@@ -7,11 +7,12 @@ namespace lbm {
 
 // One time step for every node: pull (Eqs. (18), (35)) -> wall reconstruction -> macroscopic
 // recovery (Eqs. (36), (22), (21), (23), (4)) -> collision (Eqs. (17), (34)) -> store.
-// One work-item per node; a work-group covers kTileX consecutive nodes of one row.
-template <typename R, bool PN>
-__global__ __launch_bounds__(kTileX) void step_kernel(const R* __restrict__ src,
-                                                      R* __restrict__ dst,
-                                                      const R* __restrict__ med, Geo G,
+// One work-item per node; a work-group covers kTileX consecutive nodes of one row.  S is the
+// storage type, R the arithmetic type.
+template <typename S, typename R, bool PN>
+__global__ __launch_bounds__(kTileX) void step_kernel(const S* __restrict__ src,
+                                                      S* __restrict__ dst,
+                                                      const S* __restrict__ med, Geo G,
                                                       Phys<R> P, int tiles_x) {
     // Work-groups in launch order walk the lattice row by row.  (Dealing each XCD one
     // contiguous band of rows instead was measured 7% slower: it concentrates each XCD's
@@ -23,13 +24,14 @@ __global__ __launch_bounds__(kTileX) void step_kernel(const R* __restrict__ src,
     R f[9], g[5];
     Mac<R> m;
     Med<R> md;
-    node_state<R, PN>(src, med, G, P, x, y, f, g, m, md);
+    node_state<R, PN, S>(src, med, G, P, x, y, f, g, m, md);
     collide<R>(f, g, m, md, P);
     const int o = y * G.pitch + x;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(f[i], dst + i * G.plane + o);
+    for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(S(f[i]), dst + i * G.plane + o);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) __builtin_nontemporal_store(g[i], dst + (9 + i) * G.plane + o);
+    for (int i = 0; i < 5; ++i)
+        __builtin_nontemporal_store(S(g[i]), dst + (9 + i) * G.plane + o);
 }
 
 // Wave-level reductions over the 64 lanes of a wavefront.
@@ -47,13 +49,13 @@ __device__ __forceinline__ double wave_max(double v) {
 // Macroscopic fields at the current time level, plus per-work-group partial results:
 // part[3 * b + 0] = max |u|, part[3 * b + 1] = sum of stored f' (mass deviation),
 // part[3 * b + 2] = 1 if a field is not finite.  Grid-stride over nodes.
-template <typename R, bool PN>
-__global__ __launch_bounds__(256) void observe_kernel(const R* __restrict__ src,
-                                                      const R* __restrict__ med, Geo G,
-                                                      Phys<R> P, R* __restrict__ ux_out,
-                                                      R* __restrict__ uy_out,
-                                                      R* __restrict__ p_out,
-                                                      R* __restrict__ T_out,
+template <typename S, typename R, bool PN>
+__global__ __launch_bounds__(256) void observe_kernel(const S* __restrict__ src,
+                                                      const S* __restrict__ med, Geo G,
+                                                      Phys<R> P, S* __restrict__ ux_out,
+                                                      S* __restrict__ uy_out,
+                                                      S* __restrict__ p_out,
+                                                      S* __restrict__ T_out,
                                                       double* __restrict__ part) {
     const int n = G.nx * G.ny;
     double umax = 0.0, mass = 0.0, bad = 0.0;
@@ -62,13 +64,15 @@ __global__ __launch_bounds__(256) void observe_kernel(const R* __restrict__ src,
         R f[9], g[5];
         Mac<R> m;
         Med<R> md;
-        node_state<R, PN>(src, med, G, P, x, y, f, g, m, md);
-        const R p = (m.P + P.rho0 * R(1.0 / 3.0)) * md.inv_phi;
+        node_state<R, PN, S>(src, med, G, P, x, y, f, g, m, md);
+        // the pressure of Eq. (23) less its rest value rho0 cs^2 / phi: FP32 could not hold
+        // the dynamic part, often below 1e-3 of p, on top of that background
+        const R p = m.P * md.inv_phi;
         const R T = P.T0 + m.theta;
-        if (ux_out) ux_out[k] = m.ux;
-        if (uy_out) uy_out[k] = m.uy;
-        if (p_out) p_out[k] = p;
-        if (T_out) T_out[k] = T;
+        if (ux_out) ux_out[k] = S(m.ux);
+        if (uy_out) uy_out[k] = S(m.uy);
+        if (p_out) p_out[k] = S(p);
+        if (T_out) T_out[k] = S(T);
         const double sp = sqrt(double(m.ux) * double(m.ux) + double(m.uy) * double(m.uy));
         umax = fmax(umax, sp);
         if (!isfinite(sp) || !isfinite(double(p)) || !isfinite(double(T))) bad = 1.0;
@@ -103,8 +107,8 @@ __global__ __launch_bounds__(256) void observe_kernel(const R* __restrict__ src,
 }
 
 // Temperature deviation theta = T - T0 at (x, y) after streaming and wall reconstruction.
-template <typename R>
-__device__ __forceinline__ double node_theta(const R* __restrict__ src, const Geo& G,
+template <typename S, typename R>
+__device__ __forceinline__ double node_theta(const S* __restrict__ src, const Geo& G,
                                              const Phys<R>& P, int x, int y) {
     const bool onW = G.wallW && x == 0;
     const bool onE = G.wallE && x == G.nx - 1;
@@ -113,7 +117,7 @@ __device__ __forceinline__ double node_theta(const R* __restrict__ src, const Ge
     const int xf = x + (onW ? 1 : 0) - (onE ? 1 : 0);
     const int yf = y + (onS ? 1 : 0) - (onN ? 1 : 0);
     R f[9], g[5];
-    pull<R>(src, G, xf, yf, f, g);
+    pull<R, S>(src, G, xf, yf, f, g);
     const R th = ((g[0] + g[1]) + (g[2] + g[3]) + g[4]) + P.hQs;
     if (!(onW || onE || onS || onN)) return double(th);
     return double(wall_theta<R>(onW, onE, onS, onN, th, P));
@@ -124,8 +128,8 @@ __device__ __forceinline__ double node_theta(const R* __restrict__ src, const Ge
 // ny wall nodes; part[0..2] = partial results of observe_kernel (nparts work-groups).
 // One work-group; writes out[0] nu_hot, out[1] nu_cold, out[2] max |u|, out[3] sum f',
 // out[4] non-finite flag.
-template <typename R>
-__global__ __launch_bounds__(256) void nusselt_kernel(const R* __restrict__ src, Geo G,
+template <typename S, typename R>
+__global__ __launch_bounds__(256) void nusselt_kernel(const S* __restrict__ src, Geo G,
                                                       Phys<R> P, double L_over_dT,
                                                       const double* __restrict__ part,
                                                       int nparts, double* __restrict__ out) {
@@ -135,8 +139,8 @@ __global__ __launch_bounds__(256) void nusselt_kernel(const R* __restrict__ src,
             double Th[5], Tc[5];
 #pragma unroll
             for (int k = 0; k < 5; ++k) {
-                Th[k] = node_theta<R>(src, G, P, k, y);
-                Tc[k] = node_theta<R>(src, G, P, G.nx - 1 - k, y);
+                Th[k] = node_theta<S, R>(src, G, P, k, y);
+                Tc[k] = node_theta<S, R>(src, G, P, G.nx - 1 - k, y);
             }
             const double dh = (-25.0 * Th[0] + 48.0 * Th[1] - 36.0 * Th[2] + 16.0 * Th[3] -
                                3.0 * Th[4]) / 12.0;
@@ -179,9 +183,9 @@ __global__ __launch_bounds__(256) void nusselt_kernel(const R* __restrict__ src,
 
 // Stream function: one work-item per column x integrates u_x (Eq. (21)) along y with the
 // trapezoid rule, psi(x, 0) = 0.
-template <typename R, bool PN>
-__global__ void stream_function_kernel(const R* __restrict__ src, const R* __restrict__ med,
-                                       Geo G, Phys<R> P, R* __restrict__ psi) {
+template <typename S, typename R, bool PN>
+__global__ void stream_function_kernel(const S* __restrict__ src, const S* __restrict__ med,
+                                       Geo G, Phys<R> P, S* __restrict__ psi) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= G.nx) return;
     double acc = 0.0, prev = 0.0;
@@ -189,11 +193,11 @@ __global__ void stream_function_kernel(const R* __restrict__ src, const R* __res
         R f[9], g[5];
         Mac<R> m;
         Med<R> md;
-        node_state<R, PN>(src, med, G, P, x, y, f, g, m, md);
+        node_state<R, PN, S>(src, med, G, P, x, y, f, g, m, md);
         const double u = double(m.ux);
         if (y > 0) acc += 0.5 * (prev + u);
         prev = u;
-        psi[y * G.nx + x] = R(acc);
+        psi[y * G.nx + x] = S(acc);
     }
 }
 
@@ -222,46 +226,46 @@ __global__ void pitch_copy_kernel(R* __restrict__ dst, const R* __restrict__ src
 
 // ---- launchers --------------------------------------------------------------------------------
 
-template <typename R>
+template <typename S, typename R>
 hipError_t launch_step(const void* src, void* dst, const void* med, const Geo& G,
                        const Phys<R>& P, hipStream_t s) {
     const int tiles_x = (G.nx + kTileX - 1) / kTileX;
     const int nwg = tiles_x * G.ny;
     if (med)
-        step_kernel<R, true><<<nwg, kTileX, 0, s>>>((const R*)src, (R*)dst, (const R*)med, G, P,
-                                                    tiles_x);
+        step_kernel<S, R, true><<<nwg, kTileX, 0, s>>>((const S*)src, (S*)dst, (const S*)med, G,
+                                                       P, tiles_x);
     else
-        step_kernel<R, false><<<nwg, kTileX, 0, s>>>((const R*)src, (R*)dst, nullptr, G, P,
-                                                     tiles_x);
+        step_kernel<S, R, false><<<nwg, kTileX, 0, s>>>((const S*)src, (S*)dst, nullptr, G, P,
+                                                        tiles_x);
     return hipGetLastError();
 }
 
-template <typename R>
+template <typename S, typename R>
 hipError_t launch_observe(const void* src, const void* med, const Geo& G, const Phys<R>& P,
                           void* ux, void* uy, void* p, void* T, double* part, int nparts,
                           double L_over_dT, double* out, hipStream_t s) {
     if (med)
-        observe_kernel<R, true><<<nparts, 256, 0, s>>>((const R*)src, (const R*)med, G, P,
-                                                       (R*)ux, (R*)uy, (R*)p, (R*)T, part);
+        observe_kernel<S, R, true><<<nparts, 256, 0, s>>>((const S*)src, (const S*)med, G, P,
+                                                          (S*)ux, (S*)uy, (S*)p, (S*)T, part);
     else
-        observe_kernel<R, false><<<nparts, 256, 0, s>>>((const R*)src, nullptr, G, P, (R*)ux,
-                                                        (R*)uy, (R*)p, (R*)T, part);
+        observe_kernel<S, R, false><<<nparts, 256, 0, s>>>((const S*)src, nullptr, G, P, (S*)ux,
+                                                           (S*)uy, (S*)p, (S*)T, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    nusselt_kernel<R><<<1, 256, 0, s>>>((const R*)src, G, P, L_over_dT, part, nparts, out);
+    nusselt_kernel<S, R><<<1, 256, 0, s>>>((const S*)src, G, P, L_over_dT, part, nparts, out);
     return hipGetLastError();
 }
 
-template <typename R>
+template <typename S, typename R>
 hipError_t launch_stream_function(const void* src, const void* med, const Geo& G,
                                   const Phys<R>& P, void* psi, hipStream_t s) {
     const int nb = (G.nx + 63) / 64;
     if (med)
-        stream_function_kernel<R, true><<<nb, 64, 0, s>>>((const R*)src, (const R*)med, G, P,
-                                                          (R*)psi);
+        stream_function_kernel<S, R, true><<<nb, 64, 0, s>>>((const S*)src, (const S*)med, G, P,
+                                                             (S*)psi);
     else
-        stream_function_kernel<R, false><<<nb, 64, 0, s>>>((const R*)src, nullptr, G, P,
-                                                           (R*)psi);
+        stream_function_kernel<S, R, false><<<nb, 64, 0, s>>>((const S*)src, nullptr, G, P,
+                                                              (S*)psi);
     return hipGetLastError();
 }
 
@@ -277,20 +281,18 @@ hipError_t launch_pitch_copy(void* dst, const void* src, const Geo& G, double v,
     return hipGetLastError();
 }
 
-template hipError_t launch_step<float>(const void*, void*, const void*, const Geo&,
-                                       const Phys<float>&, hipStream_t);
-template hipError_t launch_step<double>(const void*, void*, const void*, const Geo&,
-                                        const Phys<double>&, hipStream_t);
-template hipError_t launch_observe<float>(const void*, const void*, const Geo&,
-                                          const Phys<float>&, void*, void*, void*, void*,
-                                          double*, int, double, double*, hipStream_t);
-template hipError_t launch_observe<double>(const void*, const void*, const Geo&,
-                                           const Phys<double>&, void*, void*, void*, void*,
-                                           double*, int, double, double*, hipStream_t);
-template hipError_t launch_stream_function<float>(const void*, const void*, const Geo&,
-                                                  const Phys<float>&, void*, hipStream_t);
-template hipError_t launch_stream_function<double>(const void*, const void*, const Geo&,
-                                                   const Phys<double>&, void*, hipStream_t);
+#define LBM_INSTANCES(S, R)                                                                      \
+    template hipError_t launch_step<S, R>(const void*, void*, const void*, const Geo&,           \
+                                          const Phys<R>&, hipStream_t);                          \
+    template hipError_t launch_observe<S, R>(const void*, const void*, const Geo&,               \
+                                             const Phys<R>&, void*, void*, void*, void*,         \
+                                             double*, int, double, double*, hipStream_t);        \
+    template hipError_t launch_stream_function<S, R>(const void*, const void*, const Geo&,       \
+                                                     const Phys<R>&, void*, hipStream_t);
+LBM_INSTANCES(float, float)
+LBM_INSTANCES(double, double)
+LBM_INSTANCES(float, double)
+#undef LBM_INSTANCES
 template hipError_t launch_rest<float>(void*, const Geo&, double, double, hipStream_t);
 template hipError_t launch_rest<double>(void*, const Geo&, double, double, hipStream_t);
 template hipError_t launch_pitch_copy<float>(void*, const void*, const Geo&, double, hipStream_t);

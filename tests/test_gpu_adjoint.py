@@ -6,7 +6,7 @@ compared at every node.
 Tolerances: FP64 max-abs <= 1e-9 of max |dJ/d.| over the field (dJ/dK is ~1e-4 of dJ/dphi in
 these cavities, so its rounding floor relative to its own maximum sits near 1e-10); FP32 <= 1e-3
 of it (both gradients of the same discrete map; FP32 carries the forward's rounding into the
-backward).
+backward); FP32 storage with FP64 arithmetic <= 1e-4.
 """
 import numpy as np
 import pytest
@@ -50,20 +50,21 @@ CASES = {
 }
 
 
-@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+@pytest.mark.parametrize("dtype", ["fp64", "fp32", "fp32_f64"])
 @pytest.mark.parametrize("name", list(CASES))
 def test_adjoint_matches_oracle(name, dtype):
     extra, (nx, ny) = CASES[name]
     steps, C = (40, 7) if nx < 100 else (12, 5)
     params = dict(nx=nx, ny=ny, Ra=1e5, Pr=0.71, **extra)
     phi, K = workloads.random_medium(ny, nx, seed=31 + nx + ny, K_lo=2.0, K_hi=20.0)
-    if dtype == "fp32":
+    if dtype != "fp64":
         phi = phi.astype(np.float32).astype(np.float64)
         K = K.astype(np.float32).astype(np.float64)
     J, gphi, gK = gpu_grad(params, phi, K, steps, C, dtype)
     Jr, rphi, rK = torch_ref.grad_nu_hot(phi, K, steps, **params)
-    tol = 1e-9 if dtype == "fp64" else 1e-3
-    assert abs(J - Jr) <= (1e-11 if dtype == "fp64" else 1e-4) * max(1.0, abs(Jr))
+    tol = {"fp64": 1e-9, "fp32": 1e-3, "fp32_f64": 1e-4}[dtype]
+    Jtol = {"fp64": 1e-11, "fp32": 1e-4, "fp32_f64": 1e-5}[dtype]
+    assert abs(J - Jr) <= Jtol * max(1.0, abs(Jr))
     check(gphi, rphi, tol, f"{name} dJ/dphi")
     check(gK, rK, tol, f"{name} dJ/dK")
 

@@ -34,7 +34,7 @@ def small_batch(dtype):
     return params, phis
 
 
-@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+@pytest.mark.parametrize("dtype", ["fp32", "fp64", "fp32_f64"])
 def test_batch_equals_standalone_runs_bitwise(dtype, tmp_path):
     params, phis = small_batch(dtype)
     b = Batch(params, phis, tune_cache_path=str(tmp_path / "tune.txt"))
@@ -63,7 +63,7 @@ def test_batch_subset_against_oracle():
         p.pop("dtype")
         lat = ref.RefLattice(phi_uniform=phis[i], **p)
         lat.step(40)
-        r = lat.observables()
+        r = lat.observables(dynamic_pressure=True)
         g = b.fields(i)
         for k in FIELDS:
             assert np.abs(g[k].cpu().numpy() - r[k]).max() <= 1e-12, (i, k)

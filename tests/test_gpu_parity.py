@@ -3,11 +3,13 @@ inputs: u_x, u_y, p, T at every node and the two wall Nusselt numbers (Eq. (38))
 
 Tolerances: FP64 max-abs 1e-12 after short runs on tiny grids and 1e-10 after the 20k steps of
 the 64 x 64 cavity; FP32 1e-4 of each field's range (range = max - min of the oracle's field)
-and Nu within 1e-3.  In the first steps a field's range can be far below its magnitude (p is
-~0.8 everywhere while its range is ~1e-4), where an FP32 output cannot even represent it to 1e-4
-of the range; there the range is floored at 1e-2 of the field's magnitude, so the bar never
-drops below ~15 FP32 ulps of the value.  For FP32 runs the oracle receives the FP32-rounded phi
-and K, so only the arithmetic differs.
+and Nu within 1e-3; FP32 storage with FP64 arithmetic ("fp32_f64") 1e-5 and 1e-4.  p is the pressure of Eq. (23) less its rest value rho0 cs^2 / phi, as the
+library reports it (the oracle's p is converted in FP64).  FP32 compares p up to a constant:
+the density is fixed at rho0, only pressure differences enter the momentum equation and nothing
+pins the level, which rounding moves.  In the first steps a field's range can be far below its
+magnitude; there the range is floored at 1e-2 of the field's magnitude, so the bar never drops
+below ~15 FP32 ulps of the value.  For FP32-storage runs the oracle receives the FP32-rounded
+phi and K, so only the arithmetic and the storage differ.
 """
 import numpy as np
 import pytest
@@ -19,12 +21,16 @@ from paper_1308_2071_amd import Cavity, workloads
 pytestmark = pytest.mark.gpu
 
 FIELDS = ("ux", "uy", "p", "T")
+FP32_STORAGE = ("fp32", "fp32_f64")
+# FP32 storage: field tolerance as a fraction of the range, and Nu; FP64 arithmetic on FP32
+# storage ("fp32_f64") rounds each stored value once per step and is held to a 10x tighter bar
+RTOL = {"fp32": (1e-4, 1e-3), "fp32_f64": (1e-5, 1e-4)}
 
 
 def run_pair(params, steps, phi=None, K=None, phi_u=0.6, dtype="fp64", chunks=None):
     """Run the same cavity on the GPU and in the oracle; yields (gpu_obs, ref_obs) at each
     chunk boundary."""
-    if dtype == "fp32":
+    if dtype in FP32_STORAGE:
         phi = None if phi is None else phi.astype(np.float32).astype(np.float64)
         K = None if K is None else K.astype(np.float32).astype(np.float64)
         phi_u = float(np.float32(phi_u))
@@ -38,7 +44,7 @@ def run_pair(params, steps, phi=None, K=None, phi_u=0.6, dtype="fp64", chunks=No
         cav.step(n)
         lat.step(n)
         g = cav.observables()
-        r = lat.observables()
+        r = lat.observables(dynamic_pressure=True)
         yield {k: (g[k].double().cpu().numpy() if k in FIELDS else g[k]) for k in g}, r
     cav.close()
 
@@ -51,9 +57,14 @@ def assert_match(g, r, dtype, atol64=1e-12, what="", floor=1e-2):
             assert err <= atol64, f"{what} {k}: max-abs {err:.3e} > {atol64:.1e}"
         else:
             rng = max(b.max() - b.min(), floor * np.abs(b).max(), 1e-12)
-            err = np.abs(a - b).max() / rng
-            assert err <= 1e-4, f"{what} {k}: {err:.3e} of range"
-    tol = atol64 * 100 if dtype == "fp64" else 1e-3
+            d = a - b
+            if k == "p":
+                # the pressure level is a free constant (density fixed at rho0; only pressure
+                # differences enter the momentum equation): FP32 is compared up to it
+                d = d - d.mean()
+            err = np.abs(d).max() / rng
+            assert err <= RTOL[dtype][0], f"{what} {k}: {err:.3e} of range"
+    tol = atol64 * 100 if dtype == "fp64" else RTOL[dtype][1]
     assert abs(g["nu_hot"] - r["nu_hot"]) <= tol, (what, g["nu_hot"], r["nu_hot"])
     assert abs(g["nu_cold"] - r["nu_cold"]) <= tol, (what, g["nu_cold"], r["nu_cold"])
     assert not g["diverged"]
@@ -73,7 +84,7 @@ BC_CASES = {
 }
 
 
-@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+@pytest.mark.parametrize("dtype", ["fp64", "fp32", "fp32_f64"])
 @pytest.mark.parametrize("shape", [(5, 5), (7, 6), (16, 16), (300, 70)])
 @pytest.mark.parametrize("bcname", list(BC_CASES))
 def test_tiny_grids_step_by_step(shape, bcname, dtype):
@@ -90,7 +101,7 @@ def test_tiny_grids_step_by_step(shape, bcname, dtype):
         assert_match(g, r, dtype, what=f"{bcname} {shape} chunk {i}")
 
 
-@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+@pytest.mark.parametrize("dtype", ["fp64", "fp32", "fp32_f64"])
 @pytest.mark.parametrize("forch", [0, 1])
 def test_uniform_medium_and_forchheimer_flag(dtype, forch):
     params = dict(nx=33, ny=29, Ra=1e4, Pr=1.0, Da=3e-3, forchheimer=forch)
@@ -170,7 +181,7 @@ HEAT_CASES = {
 }
 
 
-@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+@pytest.mark.parametrize("dtype", ["fp64", "fp32", "fp32_f64"])
 @pytest.mark.parametrize("name", list(HEAT_CASES))
 def test_heat_source_step_by_step(name, dtype):
     """Eqs. (30), (33), (34), (36): the heat-source term against the oracle."""

@@ -51,12 +51,13 @@ def test_periodic_box_conserves_total_mass_and_heat(oracle):
     np.testing.assert_allclose(f.sum(0), 1.0, atol=1e-14)
 
 
-def bgk_step(f, g, phi, K, d, gbeta, T0, tau_v, tau_T):
+def bgk_step(f, g, phi, K, d, gbeta, T0, tau_v, tau_T, Q=0.0):
     """Independent velocity-space LBGK with the porous equilibrium of Eq. (13)-(14), the Guo-Zhao
-    forcing and the D2Q5 equilibrium of Eq. (37a); periodic streaming.  This is the scheme the
-    MRT step must reduce to when all rates equal 1/tau (end of Sec. 3.1 and Sec. 3.2)."""
+    forcing, the D2Q5 equilibrium of Eq. (37a) and a heat source wt_i (1 - 1/(2 tau_T)) Q with
+    T = sum g + Q/2 (sigma = 1); periodic streaming.  This is the scheme the MRT step must
+    reduce to when all rates equal 1/tau (end of Sec. 3.1 and Sec. 3.2)."""
     cs2, nu = 1 / 3, d["nu"]
-    T = g.sum(0)
+    T = g.sum(0) + 0.5 * Q
     Gy = gbeta * (T - T0)
     vx = (EX[:, None, None] * f).sum(0) + 0.5 * phi * 0.0
     vy = (EY[:, None, None] * f).sum(0) + 0.5 * phi * Gy
@@ -82,7 +83,7 @@ def bgk_step(f, g, phi, K, d, gbeta, T0, tau_v, tau_T):
     gp = np.empty_like(g)
     for i in range(5):
         ge = wt[i] * T * (1 + (EX[i] * ux + EY[i] * uy) / 0.2)
-        gp[i] = g[i] - (g[i] - ge) / tau_T
+        gp[i] = g[i] - (g[i] - ge) / tau_T + (1 - 0.5 / tau_T) * wt[i] * Q
     for i in range(9):
         fp[i] = np.roll(fp[i], (EY[i], EX[i]), axis=(0, 1))
     for i in range(5):
@@ -90,15 +91,18 @@ def bgk_step(f, g, phi, K, d, gbeta, T0, tau_v, tau_T):
     return fp, gp
 
 
-def test_mrt_with_equal_rates_is_lbgk(oracle):
+@pytest.mark.parametrize("Q", [0.0, 4e-4])
+def test_mrt_with_equal_rates_is_lbgk(oracle, Q):
     """With Lambda = I / tau_v and Theta = I / tau_T the MRT scheme is the LBGK scheme with the
-    equilibria of Eq. (13) and Eq. (37a) (end of Sec. 3.1, Sec. 3.2) -- P5."""
+    equilibria of Eq. (13) and Eq. (37a) (end of Sec. 3.1, Sec. 3.2) -- P5.  With a heat source,
+    N^-1 (I - Theta/2) Psi of Eqs. (30), (34) is the velocity-space source
+    wt_i (1 - 1/(2 tau_T)) Q''' / sigma only if Psi3 = varpi Q''' / sigma."""
     nx, ny = 6, 5
     r = np.random.default_rng(2)
     phi = r.uniform(0.3, 0.9, (ny, nx))
     K = r.uniform(0.5, 5, (ny, nx))
     P = dict(nx=nx, ny=ny, bc=P_ALL, Ra=1e4, Pr=0.71, uniform_rates=1, tau_v=0.7, tau_T=0.9,
-             gbeta=2e-3)
+             gbeta=2e-3, Qv=Q)
     d = ref.derived(**P)
     lat = ref.RefLattice(phi=phi, K=K, **P)
     f, g = perturbed_state(ny, nx, 9)
@@ -110,7 +114,7 @@ def test_mrt_with_equal_rates_is_lbgk(oracle):
     for i in range(5):
         g[i] = np.roll(g[i], (EY[i], EX[i]), axis=(0, 1))
     for _ in range(100):
-        f, g = bgk_step(f, g, phi, K, d, 2e-3, d["T0"], 0.7, 0.9)
+        f, g = bgk_step(f, g, phi, K, d, 2e-3, d["T0"], 0.7, 0.9, Q)
     lat.step(100)
     fo, go = lat.get_state()
     # oracle holds post-collision values; stream them to compare with the BGK post-stream ones
@@ -246,12 +250,16 @@ def test_shear_wave_decay_rate(oracle):
     assert errs[0] / errs[1] > 3.0, errs
 
 
-def test_thermal_mode_decay_rate(oracle):
-    """T - T0 = A sin(k x) at rest decays at alpha_e k^2 with alpha_e = sigma (4 + varpi)/10
-    (tau_T - 1/2), Eq. (A9) (P9); second order in k."""
+@pytest.mark.parametrize("sigma,derived", [(1.0, False), (0.7, True)])
+def test_thermal_mode_decay_rate(oracle, sigma, derived):
+    """T - T0 = A sin(k x) at rest decays at alpha_e k^2 / sigma (Eq. (3)) with alpha_e =
+    sigma (4 + varpi)/10 (tau_T - 1/2) (Eq. (A9)) (P9); second order in k.  With tau_T derived
+    from the problem statement, alpha_e must equal nu / Pr (definition of Pr, Sec. 2)."""
     errs = []
     for n in (32, 64):
-        P = dict(nx=n, ny=4, bc=P_ALL, tau_v=0.8, tau_T=0.9, gbeta=0.0, T_init=0.5)
+        P = dict(nx=n, ny=4, bc=P_ALL, tau_v=0.8, tau_T=0.9, gbeta=0.0, T_init=0.5, sigma=sigma)
+        if derived:
+            P.update(tau_v=-1.0, tau_T=-1.0, Ra=1e3, Pr=2.0)
         lat = ref.RefLattice(phi_uniform=0.6, **P)
         k = 2 * np.pi / n
         T = 0.5 + 0.1 * np.sin(k * np.arange(n))
@@ -264,8 +272,12 @@ def test_thermal_mode_decay_rate(oracle):
         lat.step(1000)
         a2 = mode_amplitude(lat.observables()["T"].T - 0.5, n, 0)
         rate = np.log(a1 / a2) / 1000
-        alpha = 1.0 * (4 - 2) / 10 * (0.9 - 0.5)
-        errs.append(abs(rate - alpha * k * k) / (alpha * k * k))
+        if derived:
+            alpha = ref.derived(**P)["nu"] / 2.0          # alpha_e = nu / Pr
+        else:
+            alpha = sigma * (4 - 2) / 10 * (0.9 - 0.5)    # Eq. (A9)
+        want = alpha * k * k / sigma
+        errs.append(abs(rate - want) / want)
     assert errs[-1] < 2e-3, errs
     assert errs[0] / errs[1] > 3.0, errs
 
