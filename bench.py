@@ -231,14 +231,14 @@ def leg_porous256(torch, steps=2000):
 KERNEL_NAME = {"fp32": "step_kernel<float,float,true>", "fp32_f64": "step_kernel<float,double,true>"}
 
 
-def roofline_run(torch, w, dtype, steps, warmup):
+def roofline_run(torch, w, dtype, steps, warmup, layout="pull"):
     """The roofline workload (per-node phi and K, FP32 storage) stepped `steps` times after
     `warmup`; achieved GB/s at the algorithmic 120 B per node update."""
     from paper_1308_2071_amd import Cavity
     nodes = w["params"]["nx"] * w["params"]["ny"]
     phi32 = torch.tensor(w["phi"], dtype=torch.float32)
     K32 = torch.tensor(w["K"], dtype=torch.float32)
-    cav = Cavity(dict(w["params"], dtype=dtype), phi=phi32, K=K32)
+    cav = Cavity(dict(w["params"], dtype=dtype, layout=layout), phi=phi32, K=K32)
     if warmup:
         cav.step(warmup)
     torch.cuda.synchronize()
@@ -321,6 +321,15 @@ def main():
             "ms_per_step": round(o["ms"], 5),
             "hbm_pct": round(100.0 * o["achieved"] / HBM_PEAK_GBS, 2),
             "kernel": KERNEL_NAME[other], "nu_hot": o["obs"]["nu_hot"],
+            "vs_headline": round(o["mlups"] / mlups, 3)}
+        print("# roofline workload, AA layout", file=sys.stderr, flush=True)
+        o = roofline_run(torch, w, args.dtype, min(args.steps, 1000), args.warmup, layout="aa")
+        result["roofline_aa_layout"] = {
+            "layout": "AA pattern, one buffer in place (half the state memory)",
+            "steps": min(args.steps, 1000), "value": round(o["mlups"], 1), "unit": "MLUPS",
+            "ms_per_step": round(o["ms"], 5),
+            "hbm_pct": round(100.0 * o["achieved"] / HBM_PEAK_GBS, 2),
+            "kernel": "aa_step_kernel", "nu_hot": o["obs"]["nu_hot"],
             "vs_headline": round(o["mlups"] / mlups, 3)}
         result["batched"]["vs_roofline_run"] = round(result["batched"]["value"] / mlups, 3)
     if not args.no_cpu:

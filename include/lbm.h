@@ -56,6 +56,14 @@ typedef int32_t lbm_status;
 #define LBM_FP64 1       /* FP64 storage, FP64 arithmetic */
 #define LBM_FP32_F64 2   /* FP32 storage, FP64 arithmetic */
 
+/* Population layout in the workspace.  LBM_LAYOUT_PULL: two state buffers, streaming as a pull
+ * (Eqs. (18), (35)).  LBM_LAYOUT_AA: one buffer stepped in place by two alternating forms of
+ * the same step (the AA pattern): half the state memory, results bitwise equal to the pull
+ * layout.  The AA layout has no adjoint tape (checkpoint_every must be 0) and no batched form
+ * (LBM_E_UNSUPPORTED). */
+#define LBM_LAYOUT_PULL 0
+#define LBM_LAYOUT_AA 1
+
 /* Side conditions (Sec. 4.1, Fig. 1).  Velocity is no-slip on every non-periodic side.
  * Periodic sides come in pairs (west with east, south with north). */
 #define LBM_WALL_ISOTHERMAL 0
@@ -91,6 +99,8 @@ typedef struct {
     double Qv;               /* Q''' in lattice units when Ra_I <= 0 (default 0: no source)   */
     int32_t dtype;           /* LBM_FP32, LBM_FP64 or LBM_FP32_F64                            */
     int32_t checkpoint_every;/* 0: no adjoint tape; C > 0: checkpoint every C steps, lbm_grad on */
+    int32_t layout;          /* LBM_LAYOUT_PULL (default) or LBM_LAYOUT_AA                     */
+    int32_t pad_;            /* zero                                                         */
 } lbm_params;
 
 /* Observables at the current time level. */

@@ -12,11 +12,13 @@ from __future__ import annotations
 import ctypes as C
 
 from . import _abi
-from ._abi import (LBM_FP32, LBM_FP32_F64, LBM_FP64, LBM_PERIODIC, LBM_WALL_ADIABATIC,
-                   LBM_WALL_ISOTHERMAL, LbmError, LbmObs, LbmParams, check, library, ptr)
+from ._abi import (LBM_FP32, LBM_FP32_F64, LBM_FP64, LBM_LAYOUT_AA, LBM_LAYOUT_PULL,
+                   LBM_PERIODIC, LBM_WALL_ADIABATIC, LBM_WALL_ISOTHERMAL, LbmError, LbmObs,
+                   LbmParams, check, library, ptr)
 
 __all__ = [
     "LbmParams", "LbmObs", "LbmError", "LBM_FP32", "LBM_FP64", "LBM_FP32_F64",
+    "LBM_LAYOUT_PULL", "LBM_LAYOUT_AA",
     "LBM_WALL_ISOTHERMAL",
     "LBM_WALL_ADIABATIC", "LBM_PERIODIC", "library", "make_params", "params_dict",
     "lbm_default_params", "lbm_derived", "lbm_workspace_size", "lbm_init", "lbm_step",
@@ -161,11 +163,13 @@ def lbm_last_error() -> str:
 
 def make_params(**kw) -> LbmParams:
     """lbm_params from keyword arguments over the paper's defaults; dtype may be 'fp32', 'fp64' or
-    'fp32_f64' (FP32 storage, FP64 arithmetic)."""
+    'fp32_f64' (FP32 storage, FP64 arithmetic); layout may be 'pull' or 'aa'."""
     p = lbm_default_params()
     for k, v in kw.items():
         if k == "dtype" and isinstance(v, str):
             v = {"fp32": LBM_FP32, "fp64": LBM_FP64, "fp32_f64": LBM_FP32_F64}[v]
+        if k == "layout" and isinstance(v, str):
+            v = {"pull": LBM_LAYOUT_PULL, "aa": LBM_LAYOUT_AA}[v]
         if k in _ARRAY_FIELDS:
             arr = getattr(p, k)
             for i, x in enumerate(v):

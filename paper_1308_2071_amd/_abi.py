@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(PKG, "liblbmpm.so")
 LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_HIP = 0, -1, -2, -3
 LBM_E_DIVERGED, LBM_E_STATE, LBM_E_UNSUPPORTED = -4, -5, -6
 LBM_FP32, LBM_FP64, LBM_FP32_F64 = 0, 1, 2
+LBM_LAYOUT_PULL, LBM_LAYOUT_AA = 0, 1
 LBM_WALL_ISOTHERMAL, LBM_WALL_ADIABATIC, LBM_PERIODIC = 0, 1, 2
 
 
@@ -33,6 +34,8 @@ class LbmParams(C.Structure):
         ("Ra_I", C.c_double), ("Qv", C.c_double),
         ("dtype", C.c_int32),
         ("checkpoint_every", C.c_int32),
+        ("layout", C.c_int32),
+        ("pad_", C.c_int32),
     ]
 
 

@@ -110,6 +110,10 @@ lbm_status validate(const lbm_params& p) {
     if (p.tau_T <= 0 && !(p.Pr > 0))
         return fail(LBM_E_INVAL, "Pr must be positive to derive tau_T");
     if (p.checkpoint_every < 0) return fail(LBM_E_INVAL, "checkpoint_every must be >= 0");
+    if (p.layout != LBM_LAYOUT_PULL && p.layout != LBM_LAYOUT_AA)
+        return fail(LBM_E_INVAL, "layout %d is not LBM_LAYOUT_PULL or LBM_LAYOUT_AA", p.layout);
+    if (p.layout == LBM_LAYOUT_AA && p.checkpoint_every > 0)
+        return fail(LBM_E_UNSUPPORTED, "the AA layout has no adjoint tape");
     const Derived d = derive(p);
     if (!(d.tau_v > 0.5) || !std::isfinite(d.tau_v))
         return fail(LBM_E_INVAL, "tau_v = %.17g must exceed 1/2", d.tau_v);
@@ -202,7 +206,10 @@ Layout make_layout(const lbm_params& p, int64_t nsteps_max, bool med_planes) {
     L.off_buf[0] = o;
     o += L.state_bytes;
     L.off_buf[1] = o;
-    o += L.state_bytes;
+    if (p.layout == LBM_LAYOUT_AA)
+        L.off_buf[1] = L.off_buf[0];  // one buffer, stepped in place
+    else
+        o += L.state_bytes;
     L.off_med = o;
     if (med_planes) o += align_up(2 * size_t(G.plane) * esz);
     L.off_part = o;
@@ -307,6 +314,7 @@ lbm_status check_ctx(const lbm_ctx* c, bool want_batch) {
     return LBM_OK;
 }
 
+// One pull-layout step from src to dst.
 hipError_t step_once(lbm_ctx* c, const void* src, void* dst, hipStream_t s) {
     return with_types(c->p.dtype, [&](auto st, auto rt) {
         LBM_TYPES(st, rt)
@@ -314,8 +322,24 @@ hipError_t step_once(lbm_ctx* c, const void* src, void* dst, hipStream_t s) {
     });
 }
 
-// Capture kGraphSteps launches (an even count, so the buffers end where they started) into an
-// executable graph for the given starting buffer.
+// One step of the cavity's state from form `from`: the buffer index for the pull layout, the
+// step parity for the AA layout (the state then lives in buf(0) == buf(1)).
+hipError_t advance(lbm_ctx* c, int from, hipStream_t s) {
+    if (c->p.layout != LBM_LAYOUT_AA) return step_once(c, c->buf(from), c->buf(1 - from), s);
+    return with_types(c->p.dtype, [&](auto st, auto rt) {
+        LBM_TYPES(st, rt)
+        return launch_aa_step<S, R>(c->buf(0), c->medp(), c->G, phys<R>(c), from, s);
+    });
+}
+
+// The PopLayout form the current state is in.
+int pop_layout(const lbm_ctx* c) {
+    if (c->p.layout != LBM_LAYOUT_AA) return kPull;
+    return c->cur == 0 ? kAAOpp : kAAOwn;
+}
+
+// Capture kGraphSteps launches (an even count, so the buffers, or the AA parity, end where they
+// started) into an executable graph for the given starting buffer or parity.
 constexpr int kGraphSteps = 64;
 
 lbm_status ensure_graph(lbm_ctx* c, int start) {
@@ -325,7 +349,7 @@ lbm_status ensure_graph(lbm_ctx* c, int start) {
     hipError_t err = hipSuccess;
     int b = start;
     for (int k = 0; k < kGraphSteps && err == hipSuccess; ++k) {
-        err = step_once(c, c->buf(b), c->buf(1 - b), c->cap);
+        err = advance(c, b, c->cap);
         b = 1 - b;
     }
     hipGraph_t graph = nullptr;
@@ -372,6 +396,8 @@ lbm_status batch_layout(int32_t n, const lbm_params* p, BatchLayout* L) {
         if (p[i].dtype != dt) return fail(LBM_E_INVAL, "cavity %d: dtypes differ in a batch", i);
         if (p[i].checkpoint_every != 0)
             return fail(LBM_E_UNSUPPORTED, "cavity %d: no adjoint tape in a batch", i);
+        if (p[i].layout != LBM_LAYOUT_PULL)
+            return fail(LBM_E_UNSUPPORTED, "cavity %d: a batch uses the pull layout", i);
         const Geo G = make_geo(p[i]);
         L->off.push_back(elems);
         elems += (long long)kPlanes * G.plane;
@@ -665,6 +691,8 @@ lbm_status lbm_default_params(lbm_params* p) {
     p->Qv = 0.0;
     p->dtype = LBM_FP32;
     p->checkpoint_every = 0;
+    p->layout = LBM_LAYOUT_PULL;
+    p->pad_ = 0;
     g_err.clear();
     return LBM_OK;
 }
@@ -777,7 +805,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
             HIP_TRY(hipMemcpyAsync(c->ckpt(size_t(c->step / C)), c->buf(c->cur),
                                    c->L.state_bytes, hipMemcpyDeviceToDevice, c->stream),
                     "checkpoint copy");
-        HIP_TRY(step_once(c, c->buf(c->cur), c->buf(1 - c->cur), c->stream), "step launch");
+        HIP_TRY(advance(c, c->cur, c->stream), "step launch");
         c->cur = 1 - c->cur;
         c->step += 1;
     }
@@ -793,8 +821,8 @@ lbm_status lbm_observables(lbm_ctx* c, lbm_obs* o, void* ux, void* uy, void* p, 
     const double LdT = c->d.L / c->d.dT;
     hipError_t e = with_types(c->p.dtype, [&](auto st, auto rt) {
         LBM_TYPES(st, rt)
-        return launch_observe<S, R>(c->buf(c->cur), c->medp(), c->G, phys<R>(c), ux, uy, p, T,
-                                    part, kObserveWG, LdT, res, c->stream);
+        return launch_observe<S, R>(c->buf(c->cur), c->medp(), c->G, phys<R>(c), pop_layout(c),
+                                    ux, uy, p, T, part, kObserveWG, LdT, res, c->stream);
     });
     if (e != hipSuccess) return hip_fail(e, "observables launch");
     double h[5];
@@ -821,8 +849,8 @@ lbm_status lbm_stream_function(lbm_ctx* c, void* psi) {
     if (!psi) return fail(LBM_E_INVAL, "null psi");
     hipError_t e = with_types(c->p.dtype, [&](auto st, auto rt) {
         LBM_TYPES(st, rt)
-        return launch_stream_function<S, R>(c->buf(c->cur), c->medp(), c->G, phys<R>(c), psi,
-                                            c->stream);
+        return launch_stream_function<S, R>(c->buf(c->cur), c->medp(), c->G, phys<R>(c),
+                                            pop_layout(c), psi, c->stream);
     });
     if (e != hipSuccess) return hip_fail(e, "stream function launch");
     HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
@@ -843,7 +871,8 @@ lbm_status lbm_save(lbm_ctx* c, void* host_buf, size_t bytes) {
     if (s != LBM_OK) return s;
     if (!host_buf || bytes < c->L.state_bytes + 64)
         return fail(LBM_E_INVAL, "buffer of %zu bytes < %zu", bytes, c->L.state_bytes + 64);
-    int64_t hdr[8] = {0x4C424D50, c->p.dtype, c->p.nx, c->p.ny, c->G.pitch, c->step, 0, 0};
+    int64_t hdr[8] = {0x4C424D50, c->p.dtype, c->p.nx, c->p.ny, c->G.pitch, c->step, c->p.layout,
+                      0};
     std::memcpy(host_buf, hdr, sizeof hdr);
     HIP_TRY(hipMemcpyAsync((char*)host_buf + 64, c->buf(c->cur), c->L.state_bytes,
                            hipMemcpyDeviceToHost, c->stream),
@@ -862,13 +891,14 @@ lbm_status lbm_load(lbm_ctx* c, const void* host_buf, size_t bytes) {
     int64_t hdr[8];
     std::memcpy(hdr, host_buf, sizeof hdr);
     if (hdr[0] != 0x4C424D50 || hdr[1] != c->p.dtype || hdr[2] != c->p.nx || hdr[3] != c->p.ny ||
-        hdr[4] != c->G.pitch)
+        hdr[4] != c->G.pitch || hdr[6] != c->p.layout || hdr[5] < 0)
         return fail(LBM_E_INVAL, "saved state does not match this context");
     HIP_TRY(hipMemcpyAsync(c->buf(c->cur), (const char*)host_buf + 64, c->L.state_bytes,
                            hipMemcpyHostToDevice, c->stream),
             "load copy");
     HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
     c->step = hdr[5];
+    if (c->p.layout == LBM_LAYOUT_AA) c->cur = int(c->step % 2);  // the form the state is in
     return LBM_OK;
 }
 
@@ -1056,9 +1086,9 @@ lbm_status lbm_batch_observables(lbm_ctx* c, lbm_obs* o) {
         double* res = part + 3 * kBatchObsWG;
         hipError_t e = with_types(c->p.dtype, [&](auto st, auto rt) {
             LBM_TYPES(st, rt)
-            return launch_observe<S, R>(src, nullptr, c->bG[i], bphys<R>(c, i), nullptr, nullptr,
-                                        nullptr, nullptr, part, kBatchObsWG, c->bLdT[i], res,
-                                        c->stream);
+            return launch_observe<S, R>(src, nullptr, c->bG[i], bphys<R>(c, i), kPull, nullptr,
+                                        nullptr, nullptr, nullptr, part, kBatchObsWG, c->bLdT[i],
+                                        res, c->stream);
         });
         if (e != hipSuccess) return hip_fail(e, "batch observables launch");
     }
@@ -1096,8 +1126,8 @@ lbm_status lbm_batch_fields(lbm_ctx* c, int32_t i, void* ux, void* uy, void* p, 
     double* res = part + 3 * kBatchObsWG;
     hipError_t e = with_types(c->p.dtype, [&](auto st, auto rt) {
         LBM_TYPES(st, rt)
-        return launch_observe<S, R>(src, nullptr, c->bG[i], bphys<R>(c, i), ux, uy, p, T, part,
-                                    kBatchObsWG, c->bLdT[i], res, c->stream);
+        return launch_observe<S, R>(src, nullptr, c->bG[i], bphys<R>(c, i), kPull, ux, uy, p, T,
+                                    part, kBatchObsWG, c->bLdT[i], res, c->stream);
     });
     if (e != hipSuccess) return hip_fail(e, "batch fields launch");
     HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");

@@ -89,10 +89,25 @@ __device__ __forceinline__ Med<R> load_medium(const S* __restrict__ med, int idx
     }
 }
 
-// Streaming, Eqs. (18) and (35), as a pull: the population i arriving at (x, y) left
-// (x - ex_i, y - ey_i) after the previous collision.  Indices wrap, which is only ever used on
-// periodic axes: on a walled axis the node is interior, so x-1 and x+1 stay in range.
-template <typename R, typename S = R>
+// Population layouts.
+//   kPull  two buffers.  The state holds the post-collision f+_i(x) at slot (i, x); a step
+//          gathers f_i(x) = f+_i(x - e_i) (streaming as a pull) and writes slot (i, x) of the
+//          other buffer.
+//   AA pattern, one buffer, two alternating forms of the same step:
+//   kAAOpp the state holds f+_i(x) at slot (opp(i), x) (after an even number of steps; the
+//          rest state, symmetric in i <-> opp(i), is both).  The step gathers f_i(x) from
+//          (opp(i), x - e_i) and writes f+_i(x) to (i, x + e_i), its streamed position.
+//   kAAOwn the state holds the streamed f_i(x) at slot (i, x) (after an odd number of steps).
+//          The step gathers in place and writes f+_i(x) to (opp(i), x).
+// In both AA forms the slots a node's step writes are exactly the slots it read, so one
+// buffer suffices.
+enum PopLayout { kPull = 0, kAAOpp = 1, kAAOwn = 2 };
+
+// Streaming, Eqs. (18) and (35): the populations arriving at (x, y), i.e. those that left
+// (x - ex_i, y - ey_i) after the previous collision, as the layout L stores them.  Indices
+// wrap, which is only ever used on periodic axes: on a walled axis the node is interior, so
+// x-1 and x+1 stay in range.
+template <typename R, typename S = R, int L = kPull>
 __device__ __forceinline__ void pull(const S* __restrict__ src, const Geo& G, int x, int y,
                                      R f[9], R g[5]) {
     const int xm = (x == 0) ? G.nx - 1 : x - 1;
@@ -101,20 +116,30 @@ __device__ __forceinline__ void pull(const S* __restrict__ src, const Geo& G, in
     const int rp = ((y == G.ny - 1) ? 0 : y + 1) * G.pitch;
     const int r0 = y * G.pitch;
     const int P = G.plane;
+    if constexpr (L == kAAOwn) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = R(src[i * P + r0 + x]);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) g[i] = R(src[(9 + i) * P + r0 + x]);
+        return;
+    }
+    // plane holding direction i: i itself (kPull) or opp(i) (kAAOpp); D2Q9 opposites
+    // 1 <-> 3, 2 <-> 4, 5 <-> 7, 6 <-> 8, D2Q5 likewise for 1..4
+    constexpr bool O = (L == kAAOpp);
     f[0] = R(src[0 * P + r0 + x]);
-    f[1] = R(src[1 * P + r0 + xm]);
-    f[2] = R(src[2 * P + rm + x]);
-    f[3] = R(src[3 * P + r0 + xp]);
-    f[4] = R(src[4 * P + rp + x]);
-    f[5] = R(src[5 * P + rm + xm]);
-    f[6] = R(src[6 * P + rm + xp]);
-    f[7] = R(src[7 * P + rp + xp]);
-    f[8] = R(src[8 * P + rp + xm]);
+    f[1] = R(src[(O ? 3 : 1) * P + r0 + xm]);
+    f[2] = R(src[(O ? 4 : 2) * P + rm + x]);
+    f[3] = R(src[(O ? 1 : 3) * P + r0 + xp]);
+    f[4] = R(src[(O ? 2 : 4) * P + rp + x]);
+    f[5] = R(src[(O ? 7 : 5) * P + rm + xm]);
+    f[6] = R(src[(O ? 8 : 6) * P + rm + xp]);
+    f[7] = R(src[(O ? 5 : 7) * P + rp + xp]);
+    f[8] = R(src[(O ? 6 : 8) * P + rp + xm]);
     g[0] = R(src[9 * P + r0 + x]);
-    g[1] = R(src[10 * P + r0 + xm]);
-    g[2] = R(src[11 * P + rm + x]);
-    g[3] = R(src[12 * P + r0 + xp]);
-    g[4] = R(src[13 * P + rp + x]);
+    g[1] = R(src[(O ? 12 : 10) * P + r0 + xm]);
+    g[2] = R(src[(O ? 13 : 11) * P + rm + x]);
+    g[3] = R(src[(O ? 10 : 12) * P + r0 + xp]);
+    g[4] = R(src[(O ? 11 : 13) * P + rp + x]);
 }
 
 // Eqs. (36), (22), (21), (23), (4) at a fluid node, on deviation populations.
@@ -288,9 +313,28 @@ __device__ __forceinline__ R wall_theta(bool onW, bool onE, bool onS, bool onN, 
     return theta_f;
 }
 
+// Macroscopics of a wall node (on the sides flagged onW..onN) whose inward neighbour holds the
+// pulled populations f, g with macroscopics mf and medium mdf; f, g are overwritten with the
+// wall node's reconstructed populations; mdb is the wall node's own medium.
+template <typename R>
+__device__ __forceinline__ Mac<R> wall_state(bool onW, bool onE, bool onS, bool onN, R f[9],
+                                             R g[5], const Mac<R>& mf, const Med<R>& mdf,
+                                             const Med<R>& mdb, const Phys<R>& P) {
+    const R theta_b = wall_theta<R>(onW, onE, onS, onN, mf.theta, P);
+    nee_wall<R>(f, g, mf, mdf, theta_b, P);
+    Mac<R> m;
+    m.theta = theta_b;
+    m.ux = R(0);
+    m.uy = R(0);
+    m.P = mf.P;
+    m.Fx = mdb.phi * P.ax;
+    m.Fy = mdb.phi * (P.ay + P.gbeta * theta_b);
+    return m;
+}
+
 // Post-streaming, post-wall-reconstruction state of node (x, y): populations, macroscopics and
 // medium.  Wall nodes gather around their inward neighbour (the diagonal one at corners).
-template <typename R, bool PN, typename S = R>
+template <typename R, bool PN, typename S = R, int L = kPull>
 __device__ __forceinline__ void node_state(const S* __restrict__ src, const S* __restrict__ med,
                                            const Geo& G, const Phys<R>& P, int x, int y, R f[9],
                                            R g[5], Mac<R>& m, Med<R>& md) {
@@ -299,25 +343,74 @@ __device__ __forceinline__ void node_state(const S* __restrict__ src, const S* _
     const bool onS = G.wallS && y == 0;
     const bool onN = G.wallN && y == G.ny - 1;
     if (!(onW || onE || onS || onN)) {
-        pull<R, S>(src, G, x, y, f, g);
+        pull<R, S, L>(src, G, x, y, f, g);
         md = load_medium<R, PN, S>(med, y * G.pitch + x, G.plane, P);
         m = fluid_macros<R>(f, g, md, P);
         return;
     }
     const int xf = x + (onW ? 1 : 0) - (onE ? 1 : 0);
     const int yf = y + (onS ? 1 : 0) - (onN ? 1 : 0);
-    pull<R, S>(src, G, xf, yf, f, g);
+    pull<R, S, L>(src, G, xf, yf, f, g);
     const Med<R> mdf = load_medium<R, PN, S>(med, yf * G.pitch + xf, G.plane, P);
     const Mac<R> mf = fluid_macros<R>(f, g, mdf, P);
-    const R theta_b = wall_theta<R>(onW, onE, onS, onN, mf.theta, P);
-    nee_wall<R>(f, g, mf, mdf, theta_b, P);
     md = load_medium<R, PN, S>(med, y * G.pitch + x, G.plane, P);
-    m.theta = theta_b;
-    m.ux = R(0);
-    m.uy = R(0);
-    m.P = mf.P;
-    m.Fx = md.phi * P.ax;
-    m.Fy = md.phi * (P.ay + P.gbeta * theta_b);
+    m = wall_state<R>(onW, onE, onS, onN, f, g, mf, mdf, md, P);
+}
+
+// AA-pattern store of the post-collision populations of node (x, y).  After a kAAOpp gather
+// each goes to its streamed position (i, x + e_i) (wrapping on periodic axes; a target beyond
+// a walled side is dropped, as nothing would read it); after a kAAOwn gather to (opp(i), x).
+template <typename S, typename R, int L>
+__device__ __forceinline__ void aa_store(S* __restrict__ buf, const Geo& G, int x, int y,
+                                         const R f[9], const R g[5]) {
+    const int P = G.plane;
+    const int r0 = y * G.pitch;
+    if constexpr (L == kAAOwn) {
+        const int o = r0 + x;
+        buf[0 * P + o] = S(f[0]);
+        buf[3 * P + o] = S(f[1]);
+        buf[4 * P + o] = S(f[2]);
+        buf[1 * P + o] = S(f[3]);
+        buf[2 * P + o] = S(f[4]);
+        buf[7 * P + o] = S(f[5]);
+        buf[8 * P + o] = S(f[6]);
+        buf[5 * P + o] = S(f[7]);
+        buf[6 * P + o] = S(f[8]);
+        buf[9 * P + o] = S(g[0]);
+        buf[12 * P + o] = S(g[1]);
+        buf[13 * P + o] = S(g[2]);
+        buf[10 * P + o] = S(g[3]);
+        buf[11 * P + o] = S(g[4]);
+    } else {
+        const bool okE = !(G.wallE && x == G.nx - 1), okW = !(G.wallW && x == 0);
+        const bool okN = !(G.wallN && y == G.ny - 1), okS = !(G.wallS && y == 0);
+        const int xm = (x == 0) ? G.nx - 1 : x - 1;
+        const int xp = (x == G.nx - 1) ? 0 : x + 1;
+        const int rm = ((y == 0) ? G.ny - 1 : y - 1) * G.pitch;
+        const int rp = ((y == G.ny - 1) ? 0 : y + 1) * G.pitch;
+        buf[0 * P + r0 + x] = S(f[0]);
+        buf[9 * P + r0 + x] = S(g[0]);
+        if (okE) {
+            buf[1 * P + r0 + xp] = S(f[1]);
+            buf[10 * P + r0 + xp] = S(g[1]);
+        }
+        if (okN) {
+            buf[2 * P + rp + x] = S(f[2]);
+            buf[11 * P + rp + x] = S(g[2]);
+        }
+        if (okW) {
+            buf[3 * P + r0 + xm] = S(f[3]);
+            buf[12 * P + r0 + xm] = S(g[3]);
+        }
+        if (okS) {
+            buf[4 * P + rm + x] = S(f[4]);
+            buf[13 * P + rm + x] = S(g[4]);
+        }
+        if (okE && okN) buf[5 * P + rp + xp] = S(f[5]);
+        if (okW && okN) buf[6 * P + rp + xm] = S(f[6]);
+        if (okW && okS) buf[7 * P + rm + xm] = S(f[7]);
+        if (okE && okS) buf[8 * P + rm + xp] = S(f[8]);
+    }
 }
 
 }  // namespace lbm

@@ -17,13 +17,18 @@ constexpr int kPitchAlign = 64;  // row pitch in elements
 template <typename S, typename R>
 hipError_t launch_step(const void* src, void* dst, const void* med, const Geo& G,
                        const Phys<R>& P, hipStream_t s);
+// AA-pattern step in place; parity 0: the state is in the kAAOpp form, 1: kAAOwn
+template <typename S, typename R>
+hipError_t launch_aa_step(void* buf, const void* med, const Geo& G, const Phys<R>& P,
+                          int parity, hipStream_t s);
+// layout: the PopLayout form the state is in
 template <typename S, typename R>
 hipError_t launch_observe(const void* src, const void* med, const Geo& G, const Phys<R>& P,
-                          void* ux, void* uy, void* p, void* T, double* part, int nparts,
-                          double L_over_dT, double* out, hipStream_t s);
+                          int layout, void* ux, void* uy, void* p, void* T, double* part,
+                          int nparts, double L_over_dT, double* out, hipStream_t s);
 template <typename S, typename R>
 hipError_t launch_stream_function(const void* src, const void* med, const Geo& G,
-                                  const Phys<R>& P, void* psi, hipStream_t s);
+                                  const Phys<R>& P, int layout, void* psi, hipStream_t s);
 template <typename R>
 hipError_t launch_rest(void* dst, const Geo& G, double g0, double g1, hipStream_t s);
 template <typename R>

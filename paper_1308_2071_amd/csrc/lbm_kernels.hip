@@ -34,6 +34,55 @@ __global__ __launch_bounds__(kTileX) void step_kernel(const S* __restrict__ src,
         __builtin_nontemporal_store(S(g[i]), dst + (9 + i) * G.plane + o);
 }
 
+// One AA-pattern time step in place (layout L = kAAOpp or kAAOwn read, the other written).
+// The per-node arithmetic is step_kernel's.  A wall node is stepped by the thread of its inward
+// neighbour, which already holds the populations the reconstruction needs: a wall thread reading
+// them itself could see the neighbour's new values.  The thread of node x writes only slots that
+// it alone read (its own and those of the wall nodes it steps), so the step is race-free.
+template <typename S, typename R, bool PN, int L>
+__global__ __launch_bounds__(kTileX) void aa_step_kernel(S* __restrict__ buf,
+                                                         const S* __restrict__ med, Geo G,
+                                                         Phys<R> P, int tiles_x) {
+    const int t = blockIdx.x;
+    const int y = t / tiles_x;
+    const int x = (t - y * tiles_x) * kTileX + threadIdx.x;
+    if (x >= G.nx) return;
+    if ((G.wallW && x == 0) || (G.wallE && x == G.nx - 1) || (G.wallS && y == 0) ||
+        (G.wallN && y == G.ny - 1))
+        return;
+    R f[9], g[5];
+    pull<R, S, L>(buf, G, x, y, f, g);
+    const Med<R> md = load_medium<R, PN, S>(med, y * G.pitch + x, G.plane, P);
+    const Mac<R> m = fluid_macros<R>(f, g, md, P);
+    const bool nearW = G.wallW && x == 1, nearE = G.wallE && x == G.nx - 2;
+    const bool nearS = G.wallS && y == 1, nearN = G.wallN && y == G.ny - 2;
+    if (nearW || nearE || nearS || nearN) {
+        // up to three wall nodes (two sides and their corner) have (x, y) as inward neighbour
+        const int dxs[8] = {-1, 1, 0, 0, -1, 1, -1, 1};
+        const int dys[8] = {0, 0, -1, 1, -1, -1, 1, 1};
+        for (int k = 0; k < 8; ++k) {
+            const int xb = x + dxs[k], yb = y + dys[k];
+            if (xb < 0 || xb >= G.nx || yb < 0 || yb >= G.ny) continue;
+            const bool bW = G.wallW && xb == 0, bE = G.wallE && xb == G.nx - 1;
+            const bool bS = G.wallS && yb == 0, bN = G.wallN && yb == G.ny - 1;
+            if (!(bW || bE || bS || bN)) continue;
+            if (xb + (bW ? 1 : 0) - (bE ? 1 : 0) != x || yb + (bS ? 1 : 0) - (bN ? 1 : 0) != y)
+                continue;
+            R fb[9], gb[5];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) fb[i] = f[i];
+#pragma unroll
+            for (int i = 0; i < 5; ++i) gb[i] = g[i];
+            const Med<R> mdb = load_medium<R, PN, S>(med, yb * G.pitch + xb, G.plane, P);
+            const Mac<R> mb = wall_state<R>(bW, bE, bS, bN, fb, gb, m, md, mdb, P);
+            collide<R>(fb, gb, mb, mdb, P);
+            aa_store<S, R, L>(buf, G, xb, yb, fb, gb);
+        }
+    }
+    collide<R>(f, g, m, md, P);
+    aa_store<S, R, L>(buf, G, x, y, f, g);
+}
+
 // Wave-level reductions over the 64 lanes of a wavefront.
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -49,7 +98,7 @@ __device__ __forceinline__ double wave_max(double v) {
 // Macroscopic fields at the current time level, plus per-work-group partial results:
 // part[3 * b + 0] = max |u|, part[3 * b + 1] = sum of stored f' (mass deviation),
 // part[3 * b + 2] = 1 if a field is not finite.  Grid-stride over nodes.
-template <typename S, typename R, bool PN>
+template <typename S, typename R, bool PN, int L>
 __global__ __launch_bounds__(256) void observe_kernel(const S* __restrict__ src,
                                                       const S* __restrict__ med, Geo G,
                                                       Phys<R> P, S* __restrict__ ux_out,
@@ -64,7 +113,7 @@ __global__ __launch_bounds__(256) void observe_kernel(const S* __restrict__ src,
         R f[9], g[5];
         Mac<R> m;
         Med<R> md;
-        node_state<R, PN, S>(src, med, G, P, x, y, f, g, m, md);
+        node_state<R, PN, S, L>(src, med, G, P, x, y, f, g, m, md);
         // the pressure of Eq. (23) less its rest value rho0 cs^2 / phi: FP32 could not hold
         // the dynamic part, often below 1e-3 of p, on top of that background
         const R p = m.P * md.inv_phi;
@@ -107,7 +156,7 @@ __global__ __launch_bounds__(256) void observe_kernel(const S* __restrict__ src,
 }
 
 // Temperature deviation theta = T - T0 at (x, y) after streaming and wall reconstruction.
-template <typename S, typename R>
+template <typename S, typename R, int L>
 __device__ __forceinline__ double node_theta(const S* __restrict__ src, const Geo& G,
                                              const Phys<R>& P, int x, int y) {
     const bool onW = G.wallW && x == 0;
@@ -117,7 +166,7 @@ __device__ __forceinline__ double node_theta(const S* __restrict__ src, const Ge
     const int xf = x + (onW ? 1 : 0) - (onE ? 1 : 0);
     const int yf = y + (onS ? 1 : 0) - (onN ? 1 : 0);
     R f[9], g[5];
-    pull<R, S>(src, G, xf, yf, f, g);
+    pull<R, S, L>(src, G, xf, yf, f, g);
     const R th = ((g[0] + g[1]) + (g[2] + g[3]) + g[4]) + P.hQs;
     if (!(onW || onE || onS || onN)) return double(th);
     return double(wall_theta<R>(onW, onE, onS, onN, th, P));
@@ -128,7 +177,7 @@ __device__ __forceinline__ double node_theta(const S* __restrict__ src, const Ge
 // ny wall nodes; part[0..2] = partial results of observe_kernel (nparts work-groups).
 // One work-group; writes out[0] nu_hot, out[1] nu_cold, out[2] max |u|, out[3] sum f',
 // out[4] non-finite flag.
-template <typename S, typename R>
+template <typename S, typename R, int L>
 __global__ __launch_bounds__(256) void nusselt_kernel(const S* __restrict__ src, Geo G,
                                                       Phys<R> P, double L_over_dT,
                                                       const double* __restrict__ part,
@@ -139,8 +188,8 @@ __global__ __launch_bounds__(256) void nusselt_kernel(const S* __restrict__ src,
             double Th[5], Tc[5];
 #pragma unroll
             for (int k = 0; k < 5; ++k) {
-                Th[k] = node_theta<S, R>(src, G, P, k, y);
-                Tc[k] = node_theta<S, R>(src, G, P, G.nx - 1 - k, y);
+                Th[k] = node_theta<S, R, L>(src, G, P, k, y);
+                Tc[k] = node_theta<S, R, L>(src, G, P, G.nx - 1 - k, y);
             }
             const double dh = (-25.0 * Th[0] + 48.0 * Th[1] - 36.0 * Th[2] + 16.0 * Th[3] -
                                3.0 * Th[4]) / 12.0;
@@ -183,7 +232,7 @@ __global__ __launch_bounds__(256) void nusselt_kernel(const S* __restrict__ src,
 
 // Stream function: one work-item per column x integrates u_x (Eq. (21)) along y with the
 // trapezoid rule, psi(x, 0) = 0.
-template <typename S, typename R, bool PN>
+template <typename S, typename R, bool PN, int L>
 __global__ void stream_function_kernel(const S* __restrict__ src, const S* __restrict__ med,
                                        Geo G, Phys<R> P, S* __restrict__ psi) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -193,7 +242,7 @@ __global__ void stream_function_kernel(const S* __restrict__ src, const S* __res
         R f[9], g[5];
         Mac<R> m;
         Med<R> md;
-        node_state<R, PN, S>(src, med, G, P, x, y, f, g, m, md);
+        node_state<R, PN, S, L>(src, med, G, P, x, y, f, g, m, md);
         const double u = double(m.ux);
         if (y > 0) acc += 0.5 * (prev + u);
         prev = u;
@@ -240,33 +289,85 @@ hipError_t launch_step(const void* src, void* dst, const void* med, const Geo& G
     return hipGetLastError();
 }
 
+// parity 0: the state is in the kAAOpp form (even step count); 1: kAAOwn (odd)
 template <typename S, typename R>
-hipError_t launch_observe(const void* src, const void* med, const Geo& G, const Phys<R>& P,
-                          void* ux, void* uy, void* p, void* T, double* part, int nparts,
-                          double L_over_dT, double* out, hipStream_t s) {
+hipError_t launch_aa_step(void* buf, const void* med, const Geo& G, const Phys<R>& P,
+                          int parity, hipStream_t s) {
+    const int tiles_x = (G.nx + kTileX - 1) / kTileX;
+    const int nwg = tiles_x * G.ny;
+    S* b = (S*)buf;
+    const S* m = (const S*)med;
+    if (parity == 0) {
+        if (med)
+            aa_step_kernel<S, R, true, kAAOpp><<<nwg, kTileX, 0, s>>>(b, m, G, P, tiles_x);
+        else
+            aa_step_kernel<S, R, false, kAAOpp><<<nwg, kTileX, 0, s>>>(b, m, G, P, tiles_x);
+    } else {
+        if (med)
+            aa_step_kernel<S, R, true, kAAOwn><<<nwg, kTileX, 0, s>>>(b, m, G, P, tiles_x);
+        else
+            aa_step_kernel<S, R, false, kAAOwn><<<nwg, kTileX, 0, s>>>(b, m, G, P, tiles_x);
+    }
+    return hipGetLastError();
+}
+
+template <typename S, typename R, int L>
+static hipError_t observe_l(const void* src, const void* med, const Geo& G, const Phys<R>& P,
+                            void* ux, void* uy, void* p, void* T, double* part, int nparts,
+                            double L_over_dT, double* out, hipStream_t s) {
     if (med)
-        observe_kernel<S, R, true><<<nparts, 256, 0, s>>>((const S*)src, (const S*)med, G, P,
-                                                          (S*)ux, (S*)uy, (S*)p, (S*)T, part);
+        observe_kernel<S, R, true, L><<<nparts, 256, 0, s>>>(
+            (const S*)src, (const S*)med, G, P, (S*)ux, (S*)uy, (S*)p, (S*)T, part);
     else
-        observe_kernel<S, R, false><<<nparts, 256, 0, s>>>((const S*)src, nullptr, G, P, (S*)ux,
-                                                           (S*)uy, (S*)p, (S*)T, part);
+        observe_kernel<S, R, false, L><<<nparts, 256, 0, s>>>(
+            (const S*)src, nullptr, G, P, (S*)ux, (S*)uy, (S*)p, (S*)T, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    nusselt_kernel<S, R><<<1, 256, 0, s>>>((const S*)src, G, P, L_over_dT, part, nparts, out);
+    nusselt_kernel<S, R, L><<<1, 256, 0, s>>>((const S*)src, G, P, L_over_dT, part, nparts, out);
+    return hipGetLastError();
+}
+
+// layout: kPull, kAAOpp or kAAOwn, the form the state is in
+template <typename S, typename R>
+hipError_t launch_observe(const void* src, const void* med, const Geo& G, const Phys<R>& P,
+                          int layout, void* ux, void* uy, void* p, void* T, double* part,
+                          int nparts, double L_over_dT, double* out, hipStream_t s) {
+    switch (layout) {
+        case kPull:
+            return observe_l<S, R, kPull>(src, med, G, P, ux, uy, p, T, part, nparts, L_over_dT,
+                                          out, s);
+        case kAAOpp:
+            return observe_l<S, R, kAAOpp>(src, med, G, P, ux, uy, p, T, part, nparts,
+                                           L_over_dT, out, s);
+        case kAAOwn:
+            return observe_l<S, R, kAAOwn>(src, med, G, P, ux, uy, p, T, part, nparts,
+                                           L_over_dT, out, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename S, typename R, int L>
+static hipError_t stream_function_l(const void* src, const void* med, const Geo& G,
+                                    const Phys<R>& P, void* psi, hipStream_t s) {
+    const int nb = (G.nx + 63) / 64;
+    if (med)
+        stream_function_kernel<S, R, true, L><<<nb, 64, 0, s>>>((const S*)src, (const S*)med, G,
+                                                                P, (S*)psi);
+    else
+        stream_function_kernel<S, R, false, L><<<nb, 64, 0, s>>>((const S*)src, nullptr, G, P,
+                                                                 (S*)psi);
     return hipGetLastError();
 }
 
 template <typename S, typename R>
 hipError_t launch_stream_function(const void* src, const void* med, const Geo& G,
-                                  const Phys<R>& P, void* psi, hipStream_t s) {
-    const int nb = (G.nx + 63) / 64;
-    if (med)
-        stream_function_kernel<S, R, true><<<nb, 64, 0, s>>>((const S*)src, (const S*)med, G, P,
-                                                             (S*)psi);
-    else
-        stream_function_kernel<S, R, false><<<nb, 64, 0, s>>>((const S*)src, nullptr, G, P,
-                                                              (S*)psi);
-    return hipGetLastError();
+                                  const Phys<R>& P, int layout, void* psi, hipStream_t s) {
+    switch (layout) {
+        case kPull: return stream_function_l<S, R, kPull>(src, med, G, P, psi, s);
+        case kAAOpp: return stream_function_l<S, R, kAAOpp>(src, med, G, P, psi, s);
+        case kAAOwn: return stream_function_l<S, R, kAAOwn>(src, med, G, P, psi, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename R>
@@ -284,11 +385,13 @@ hipError_t launch_pitch_copy(void* dst, const void* src, const Geo& G, double v,
 #define LBM_INSTANCES(S, R)                                                                      \
     template hipError_t launch_step<S, R>(const void*, void*, const void*, const Geo&,           \
                                           const Phys<R>&, hipStream_t);                          \
+    template hipError_t launch_aa_step<S, R>(void*, const void*, const Geo&, const Phys<R>&,     \
+                                             int, hipStream_t);                                  \
     template hipError_t launch_observe<S, R>(const void*, const void*, const Geo&,               \
-                                             const Phys<R>&, void*, void*, void*, void*,         \
+                                             const Phys<R>&, int, void*, void*, void*, void*,    \
                                              double*, int, double, double*, hipStream_t);        \
     template hipError_t launch_stream_function<S, R>(const void*, const void*, const Geo&,       \
-                                                     const Phys<R>&, void*, hipStream_t);
+                                                     const Phys<R>&, int, void*, hipStream_t);
 LBM_INSTANCES(float, float)
 LBM_INSTANCES(double, double)
 LBM_INSTANCES(float, double)

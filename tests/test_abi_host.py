@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported(lbm):
 def test_param_struct_layout_matches_header(lbm):
     # the ctypes mirror must have the C layout: 8-byte aligned doubles after int32 pairs
     from paper_1308_2071_amd._abi import LbmObs, LbmParams
-    assert C.sizeof(LbmParams) == 8 + 16 + 32 + 4 * 8 + 4 * 8 + 5 * 8 + 8 + 8 + 16 + 3 * 8 + 2 * 8 + 8
+    assert C.sizeof(LbmParams) == 8 + 16 + 32 + 4 * 8 + 4 * 8 + 5 * 8 + 8 + 8 + 16 + 3 * 8 + 2 * 8 + 8 + 8
     assert C.sizeof(LbmObs) == 48
 
 
@@ -133,3 +133,19 @@ def test_workspace_grows_with_tape(lbm):
     assert base >= 2 * state
     # 20 checkpoints + 100 segment states + 2 adjoint buffers
     assert tape - base >= (20 + 100 + 2) * state
+
+
+def test_aa_layout_halves_the_state_memory(lbm):
+    pull = lbm.lbm_workspace_size(lbm.make_params(nx=300, ny=200), 0)
+    aa = lbm.lbm_workspace_size(lbm.make_params(nx=300, ny=200, layout="aa"), 0)
+    state = 14 * 200 * 320 * 4       # pitch 320 = 300 rounded up to 64
+    assert pull - aa == state
+
+
+def test_aa_layout_limits(lbm):
+    assert status_of(lbm, layout=3) == -1                          # LBM_E_INVAL
+    assert status_of(lbm, layout=1, checkpoint_every=10) == -6     # LBM_E_UNSUPPORTED: no tape
+    from paper_1308_2071_amd import _abi
+    p = (_abi.LbmParams * 1)(lbm.make_params(nx=16, ny=16, layout="aa"))
+    n = C.c_size_t()
+    assert _abi.library().lbm_batch_workspace_size(1, p, C.byref(n)) == -6
