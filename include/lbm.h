@@ -100,7 +100,10 @@ typedef struct {
     int32_t dtype;           /* LBM_FP32, LBM_FP64 or LBM_FP32_F64                            */
     int32_t checkpoint_every;/* 0: no adjoint tape; C > 0: checkpoint every C steps, lbm_grad on */
     int32_t layout;          /* LBM_LAYOUT_PULL (default) or LBM_LAYOUT_AA                     */
-    int32_t pad_;            /* zero                                                         */
+    int32_t steps_per_launch;/* 0 (default): fuse two time steps per launch where that is     */
+                             /* faster (large grids, storage type = arithmetic type); 2: fuse */
+                             /* wherever the pull layout without a tape allows; 1: one step  */
+                             /* per launch.  Results are bitwise the same in every case.      */
 } lbm_params;
 
 /* Observables at the current time level. */
@@ -163,6 +166,12 @@ lbm_status lbm_observables(lbm_ctx* c, lbm_obs* o, void* ux, void* uy, void* p, 
  * at y = 0 (the south side), from the velocity of Eq. (21); its maximum normalised by
  * L sqrt(g beta dT L) is the psi_max of Sec. 4.2 (Table 3). */
 lbm_status lbm_stream_function(lbm_ctx* c, void* psi);
+
+/* Launch shape of the time loop in use (no device work): out[0] time steps per launch (1, or
+ * 2 when two steps are fused, see steps_per_launch), out[1] the layout (LBM_LAYOUT_*),
+ * out[2] rows per wavefront segment of the fused kernel (0 when not fused), out[3]
+ * work-groups per launch.  out holds 4 entries. */
+lbm_status lbm_step_shape(const lbm_ctx* c, int32_t* out);
 
 /* Discrete adjoint (synchronises).  For J = nu_hot at the current time level n (Eq. (38)),
  * computes dJ_dphi = dJ * dJ/dphi(x) and dJ_dK = dJ * dJ/dK(x) at every node, the exact

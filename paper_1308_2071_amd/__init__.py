@@ -24,7 +24,8 @@ __all__ = [
     "lbm_default_params", "lbm_derived", "lbm_workspace_size", "lbm_init", "lbm_step",
     "lbm_observables", "lbm_grad", "lbm_stream_function", "lbm_state_size", "lbm_save", "lbm_load", "lbm_destroy",
     "lbm_batch_workspace_size", "lbm_batch_init", "lbm_batch_step", "lbm_batch_observables",
-    "lbm_batch_fields", "lbm_batch_shape", "lbm_status_string", "lbm_last_error", "Cavity", "Batch", "NuHot",
+    "lbm_batch_fields", "lbm_batch_shape", "lbm_step_shape", "lbm_status_string",
+    "lbm_last_error", "Cavity", "Batch", "NuHot",
 ]
 
 _ARRAY_FIELDS = ("bc", "T_wall", "ext_accel")
@@ -148,6 +149,12 @@ def lbm_batch_fields(ctx: int, i: int, ux=None, uy=None, p=None, T=None) -> None
 def lbm_batch_shape(ctx: int):
     out = (C.c_int32 * 4)()
     check(library().lbm_batch_shape(ctx, out), "lbm_batch_shape")
+    return tuple(out)
+
+
+def lbm_step_shape(ctx: int):
+    out = (C.c_int32 * 4)()
+    check(library().lbm_step_shape(ctx, out), "lbm_step_shape")
     return tuple(out)
 
 

@@ -35,7 +35,7 @@ class LbmParams(C.Structure):
         ("dtype", C.c_int32),
         ("checkpoint_every", C.c_int32),
         ("layout", C.c_int32),
-        ("pad_", C.c_int32),
+        ("steps_per_launch", C.c_int32),
     ]
 
 
@@ -86,6 +86,7 @@ def library() -> C.CDLL:
         "lbm_batch_observables": [vp, C.POINTER(LbmObs)],
         "lbm_batch_fields": [vp, i32, vp, vp, vp, vp],
         "lbm_batch_shape": [vp, C.POINTER(i32)],
+        "lbm_step_shape": [vp, C.POINTER(i32)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -103,7 +104,8 @@ EXPORTED = (
     "lbm_default_params", "lbm_derived", "lbm_workspace_size", "lbm_init", "lbm_step",
     "lbm_observables", "lbm_grad", "lbm_stream_function", "lbm_state_size", "lbm_save", "lbm_load", "lbm_destroy",
     "lbm_batch_workspace_size", "lbm_batch_init", "lbm_batch_step", "lbm_batch_observables",
-    "lbm_batch_fields", "lbm_batch_shape", "lbm_status_string", "lbm_last_error",
+    "lbm_batch_fields", "lbm_batch_shape", "lbm_step_shape", "lbm_status_string",
+    "lbm_last_error",
 )
 
 

@@ -112,6 +112,8 @@ lbm_status validate(const lbm_params& p) {
     if (p.checkpoint_every < 0) return fail(LBM_E_INVAL, "checkpoint_every must be >= 0");
     if (p.layout != LBM_LAYOUT_PULL && p.layout != LBM_LAYOUT_AA)
         return fail(LBM_E_INVAL, "layout %d is not LBM_LAYOUT_PULL or LBM_LAYOUT_AA", p.layout);
+    if (p.steps_per_launch < 0 || p.steps_per_launch > 2)
+        return fail(LBM_E_INVAL, "steps_per_launch = %d is not 0, 1 or 2", p.steps_per_launch);
     if (p.layout == LBM_LAYOUT_AA && p.checkpoint_every > 0)
         return fail(LBM_E_UNSUPPORTED, "the AA layout has no adjoint tape");
     const Derived d = derive(p);
@@ -283,7 +285,7 @@ struct Tag {
 
 // Calls f(Tag<S>, Tag<R>) with the storage type S and the arithmetic type R of a dtype.
 template <class F>
-hipError_t with_types(int dtype, F&& f) {
+auto with_types(int dtype, F&& f) -> decltype(f(Tag<float>{}, Tag<float>{})) {
     if (dtype == LBM_FP64) return f(Tag<double>{}, Tag<double>{});
     if (dtype == LBM_FP32_F64) return f(Tag<float>{}, Tag<double>{});
     return f(Tag<float>{}, Tag<float>{});
@@ -332,6 +334,27 @@ hipError_t advance(lbm_ctx* c, int from, hipStream_t s) {
     });
 }
 
+// Two steps in one launch from buffer `from` (pull layout only).
+hipError_t advance2(lbm_ctx* c, int from, hipStream_t s) {
+    return with_types(c->p.dtype, [&](auto st, auto rt) {
+        LBM_TYPES(st, rt)
+        return launch_tb2_step<S, R>(c->buf(from), c->buf(1 - from), c->medp(), c->G,
+                                     phys<R>(c), s);
+    });
+}
+
+// Whether the time loop fuses two steps per launch: never with the AA layout or a tape, always
+// when asked for (steps_per_launch = 2), and by default where it is measured to pay.
+bool fused(const lbm_ctx* c) {
+    if (c->p.layout != LBM_LAYOUT_PULL || c->p.checkpoint_every != 0) return false;
+    if (c->p.steps_per_launch == 1) return false;
+    if (c->p.steps_per_launch == 2) return true;
+    return with_types(c->p.dtype, [&](auto st, auto rt) {
+        LBM_TYPES(st, rt)
+        return tb2_pays<S, R>(c->G, c->med);
+    });
+}
+
 // The PopLayout form the current state is in.
 int pop_layout(const lbm_ctx* c) {
     if (c->p.layout != LBM_LAYOUT_AA) return kPull;
@@ -348,9 +371,17 @@ lbm_status ensure_graph(lbm_ctx* c, int start) {
     HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal), "begin capture");
     hipError_t err = hipSuccess;
     int b = start;
-    for (int k = 0; k < kGraphSteps && err == hipSuccess; ++k) {
-        err = advance(c, b, c->cap);
-        b = 1 - b;
+    if (fused(c)) {
+        // kGraphSteps / 2 launches: an even number of buffer swaps
+        for (int k = 0; k < kGraphSteps / 2 && err == hipSuccess; ++k) {
+            err = advance2(c, b, c->cap);
+            b = 1 - b;
+        }
+    } else {
+        for (int k = 0; k < kGraphSteps && err == hipSuccess; ++k) {
+            err = advance(c, b, c->cap);
+            b = 1 - b;
+        }
     }
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(c->cap, &graph);
@@ -692,7 +723,7 @@ lbm_status lbm_default_params(lbm_params* p) {
     p->dtype = LBM_FP32;
     p->checkpoint_every = 0;
     p->layout = LBM_LAYOUT_PULL;
-    p->pad_ = 0;
+    p->steps_per_launch = 0;
     g_err.clear();
     return LBM_OK;
 }
@@ -757,7 +788,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const void* phi, const v
     const double g1 = (4.0 + p->varpi) / 20.0 * (p->T_init - c->d.T0);
     hipError_t e = with_types(p->dtype, [&](auto st, auto rt) {
         LBM_TYPES(st, rt)
-        (void)sizeof(R);
+        prepare_tb2<S, R>();
         hipError_t e1 = hipSuccess;
         if (med) {
             char* mp = c->ws + L.off_med;
@@ -798,6 +829,13 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
             HIP_TRY(hipGraphLaunch(c->gexec[c->cur], c->stream), "graph launch");
             left -= kGraphSteps;
             c->step += kGraphSteps;
+        }
+    }
+    if (fused(c)) {
+        for (; left >= 2; left -= 2) {
+            HIP_TRY(advance2(c, c->cur, c->stream), "step launch");
+            c->cur = 1 - c->cur;
+            c->step += 2;
         }
     }
     for (; left > 0; --left) {
@@ -1131,6 +1169,27 @@ lbm_status lbm_batch_fields(lbm_ctx* c, int32_t i, void* ux, void* uy, void* p, 
     });
     if (e != hipSuccess) return hip_fail(e, "batch fields launch");
     HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
+    return LBM_OK;
+}
+
+lbm_status lbm_step_shape(const lbm_ctx* c, int32_t* out) {
+    lbm_status s = check_ctx(c, false);
+    if (s != LBM_OK) return s;
+    if (!out) return fail(LBM_E_INVAL, "null argument");
+    const bool f = fused(c);
+    out[0] = f ? 2 : 1;
+    out[1] = c->p.layout;
+    out[2] = 0;
+    out[3] = (c->G.nx + kTileX - 1) / kTileX * c->G.ny;
+    if (f)
+        (void)with_types(c->p.dtype, [&](auto st, auto rt) {
+            LBM_TYPES(st, rt)
+            int rows = 0, nwg = 0;
+            tb2_shape<S, R>(c->G, c->med, &rows, &nwg);
+            out[2] = rows;
+            out[3] = nwg;
+            return 0;
+        });
     return LBM_OK;
 }
 

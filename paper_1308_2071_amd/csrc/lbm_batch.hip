@@ -52,13 +52,14 @@ __global__ __launch_bounds__(64 * TH) void batch_step_kernel(const S* __restrict
                 Med<R> md;
                 node_state<R, false, S>(s, nullptr, C.G, P, x, y, f, g, m, md);
                 collide<R>(f, g, m, md, P);
-                const int o = y * C.G.pitch + x;
+                const unsigned o =
+                    (unsigned(y) * unsigned(C.G.pitch) + unsigned(x)) * unsigned(sizeof(S));
 #pragma unroll
                 for (int i = 0; i < 9; ++i)
-                    __builtin_nontemporal_store(S(f[i]), d + i * C.G.plane + o);
+                    __builtin_nontemporal_store(S(f[i]), &at(plane(d, i, C.G.plane), o));
 #pragma unroll
                 for (int i = 0; i < 5; ++i)
-                    __builtin_nontemporal_store(S(g[i]), d + (9 + i) * C.G.plane + o);
+                    __builtin_nontemporal_store(S(g[i]), &at(plane(d, 9 + i, C.G.plane), o));
             }
         }
     }

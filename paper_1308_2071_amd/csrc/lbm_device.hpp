@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace lbm {
 
 constexpr int kPlanes = 14;
@@ -31,6 +33,25 @@ struct Geo {
     int plane;             // elements per plane, ny * pitch
     int wallW, wallE, wallS, wallN;  // side is a wall (not periodic)
 };
+
+// Population plane i of a state buffer.  The pointer is uniform over the work-group; nodes
+// index it with an unsigned 32-bit offset (a plane holds fewer than 2^31 elements), which lets
+// the compiler address every plane from one scalar base and one vector offset per position.
+template <typename T>
+__device__ __forceinline__ T* plane(T* base, int i, int P) {
+    return base + size_t(i) * size_t(P);
+}
+
+// Element at a 32-bit byte offset from a uniform base.  A state holds fewer than 2^31
+// elements over 14 planes, so a plane is below 1.3 GB even in FP64 and the byte offset of any
+// node in it fits 32 bits; computed there, each access can use the scalar-base plus 32-bit
+// vector-offset address form.
+template <typename T>
+__device__ __forceinline__ T& at(T* base, unsigned byte_off) {
+    return *reinterpret_cast<T*>(reinterpret_cast<
+        typename std::conditional<std::is_const<T>::value, const char*, char*>::type>(base) +
+                                 byte_off);
+}
 
 template <typename R>
 struct Phys {
@@ -83,7 +104,8 @@ template <typename R, bool PN, typename S = R>
 __device__ __forceinline__ Med<R> load_medium(const S* __restrict__ med, int idx, int plane,
                                               const Phys<R>& P) {
     if constexpr (PN) {
-        return medium_from<R>(R(med[idx]), R(med[plane + idx]), P);
+        const unsigned o = unsigned(idx) * unsigned(sizeof(S));
+        return medium_from<R>(R(at(med, o)), R(at(lbm::plane(med, 1, plane), o)), P);
     } else {
         return Med<R>{P.phi, P.inv_phi, P.c_lin, P.c_nl};
     }
@@ -110,36 +132,43 @@ enum PopLayout { kPull = 0, kAAOpp = 1, kAAOwn = 2 };
 template <typename R, typename S = R, int L = kPull>
 __device__ __forceinline__ void pull(const S* __restrict__ src, const Geo& G, int x, int y,
                                      R f[9], R g[5]) {
-    const int xm = (x == 0) ? G.nx - 1 : x - 1;
-    const int xp = (x == G.nx - 1) ? 0 : x + 1;
-    const int rm = ((y == 0) ? G.ny - 1 : y - 1) * G.pitch;
-    const int rp = ((y == G.ny - 1) ? 0 : y + 1) * G.pitch;
-    const int r0 = y * G.pitch;
+    constexpr unsigned B = sizeof(S);
+    const unsigned xm = (x == 0) ? G.nx - 1 : x - 1;
+    const unsigned xp = (x == G.nx - 1) ? 0 : x + 1;
+    const unsigned rm = unsigned((y == 0) ? G.ny - 1 : y - 1) * unsigned(G.pitch);
+    const unsigned rp = unsigned((y == G.ny - 1) ? 0 : y + 1) * unsigned(G.pitch);
+    const unsigned r0 = unsigned(y) * unsigned(G.pitch);
+    const unsigned xx = unsigned(x);
     const int P = G.plane;
     if constexpr (L == kAAOwn) {
+        const unsigned o = (r0 + xx) * B;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) f[i] = R(src[i * P + r0 + x]);
+        for (int i = 0; i < 9; ++i) f[i] = R(at(plane(src, i, P), o));
 #pragma unroll
-        for (int i = 0; i < 5; ++i) g[i] = R(src[(9 + i) * P + r0 + x]);
+        for (int i = 0; i < 5; ++i) g[i] = R(at(plane(src, 9 + i, P), o));
         return;
     }
     // plane holding direction i: i itself (kPull) or opp(i) (kAAOpp); D2Q9 opposites
     // 1 <-> 3, 2 <-> 4, 5 <-> 7, 6 <-> 8, D2Q5 likewise for 1..4
     constexpr bool O = (L == kAAOpp);
-    f[0] = R(src[0 * P + r0 + x]);
-    f[1] = R(src[(O ? 3 : 1) * P + r0 + xm]);
-    f[2] = R(src[(O ? 4 : 2) * P + rm + x]);
-    f[3] = R(src[(O ? 1 : 3) * P + r0 + xp]);
-    f[4] = R(src[(O ? 2 : 4) * P + rp + x]);
-    f[5] = R(src[(O ? 7 : 5) * P + rm + xm]);
-    f[6] = R(src[(O ? 8 : 6) * P + rm + xp]);
-    f[7] = R(src[(O ? 5 : 7) * P + rp + xp]);
-    f[8] = R(src[(O ? 6 : 8) * P + rp + xm]);
-    g[0] = R(src[9 * P + r0 + x]);
-    g[1] = R(src[(O ? 12 : 10) * P + r0 + xm]);
-    g[2] = R(src[(O ? 13 : 11) * P + rm + x]);
-    g[3] = R(src[(O ? 10 : 12) * P + r0 + xp]);
-    g[4] = R(src[(O ? 11 : 13) * P + rp + x]);
+    const unsigned c00 = (r0 + xx) * B, cw = (r0 + xm) * B, ce = (r0 + xp) * B;
+    const unsigned cs = (rm + xx) * B, cn = (rp + xx) * B;
+    const unsigned csw = (rm + xm) * B, cse = (rm + xp) * B;
+    const unsigned cne = (rp + xp) * B, cnw = (rp + xm) * B;
+    f[0] = R(at(plane(src, 0, P), c00));
+    f[1] = R(at(plane(src, O ? 3 : 1, P), cw));
+    f[2] = R(at(plane(src, O ? 4 : 2, P), cs));
+    f[3] = R(at(plane(src, O ? 1 : 3, P), ce));
+    f[4] = R(at(plane(src, O ? 2 : 4, P), cn));
+    f[5] = R(at(plane(src, O ? 7 : 5, P), csw));
+    f[6] = R(at(plane(src, O ? 8 : 6, P), cse));
+    f[7] = R(at(plane(src, O ? 5 : 7, P), cne));
+    f[8] = R(at(plane(src, O ? 6 : 8, P), cnw));
+    g[0] = R(at(plane(src, 9, P), c00));
+    g[1] = R(at(plane(src, O ? 12 : 10, P), cw));
+    g[2] = R(at(plane(src, O ? 13 : 11, P), cs));
+    g[3] = R(at(plane(src, O ? 10 : 12, P), ce));
+    g[4] = R(at(plane(src, O ? 11 : 13, P), cn));
 }
 
 // Eqs. (36), (22), (21), (23), (4) at a fluid node, on deviation populations.
@@ -357,6 +386,44 @@ __device__ __forceinline__ void node_state(const S* __restrict__ src, const S* _
     m = wall_state<R>(onW, onE, onS, onN, f, g, mf, mdf, md, P);
 }
 
+// For a fluid node (x, y) that holds its pulled populations f, g, macroscopics m and medium md:
+// reconstructs and collides every wall node whose inward neighbour it is (up to three: two
+// sides and their corner) and hands each to store(xb, yb, fb, gb).  The arithmetic is
+// node_state's and collide's, so a wall node stepped this way equals one stepped by its own
+// work-item.
+template <typename R, bool PN, typename S, typename Store>
+__device__ __forceinline__ void step_wall_neighbours(const S* __restrict__ med, const Geo& G,
+                                                     const Phys<R>& P, int x, int y,
+                                                     const R f[9], const R g[5],
+                                                     const Mac<R>& m, const Med<R>& md,
+                                                     Store&& store) {
+    const bool nearW = G.wallW && x == 1, nearE = G.wallE && x == G.nx - 2;
+    const bool nearS = G.wallS && y == 1, nearN = G.wallN && y == G.ny - 2;
+    if (!(nearW || nearE || nearS || nearN)) return;
+    for (int k = 0; k < 8; ++k) {
+        // the 8 neighbours: W, E, S, N, then SW, SE, NW, NE (arithmetic, not a table: an
+        // indexed local array would live in scratch memory)
+        const int dx = k < 2 ? 2 * k - 1 : (k < 4 ? 0 : 2 * ((k - 4) & 1) - 1);
+        const int dy = k < 2 ? 0 : (k < 4 ? 2 * (k - 2) - 1 : 2 * ((k - 4) >> 1) - 1);
+        const int xb = x + dx, yb = y + dy;
+        if (xb < 0 || xb >= G.nx || yb < 0 || yb >= G.ny) continue;
+        const bool bW = G.wallW && xb == 0, bE = G.wallE && xb == G.nx - 1;
+        const bool bS = G.wallS && yb == 0, bN = G.wallN && yb == G.ny - 1;
+        if (!(bW || bE || bS || bN)) continue;
+        if (xb + (bW ? 1 : 0) - (bE ? 1 : 0) != x || yb + (bS ? 1 : 0) - (bN ? 1 : 0) != y)
+            continue;
+        R fb[9], gb[5];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) fb[i] = f[i];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) gb[i] = g[i];
+        const Med<R> mdb = load_medium<R, PN, S>(med, yb * G.pitch + xb, G.plane, P);
+        const Mac<R> mb = wall_state<R>(bW, bE, bS, bN, fb, gb, m, md, mdb, P);
+        collide<R>(fb, gb, mb, mdb, P);
+        store(xb, yb, fb, gb);
+    }
+}
+
 // AA-pattern store of the post-collision populations of node (x, y).  After a kAAOpp gather
 // each goes to its streamed position (i, x + e_i) (wrapping on periodic axes; a target beyond
 // a walled side is dropped, as nothing would read it); after a kAAOwn gather to (opp(i), x).
@@ -364,52 +431,46 @@ template <typename S, typename R, int L>
 __device__ __forceinline__ void aa_store(S* __restrict__ buf, const Geo& G, int x, int y,
                                          const R f[9], const R g[5]) {
     const int P = G.plane;
-    const int r0 = y * G.pitch;
+    const unsigned r0 = unsigned(y) * unsigned(G.pitch);
+    const unsigned xx = unsigned(x);
     if constexpr (L == kAAOwn) {
-        const int o = r0 + x;
-        buf[0 * P + o] = S(f[0]);
-        buf[3 * P + o] = S(f[1]);
-        buf[4 * P + o] = S(f[2]);
-        buf[1 * P + o] = S(f[3]);
-        buf[2 * P + o] = S(f[4]);
-        buf[7 * P + o] = S(f[5]);
-        buf[8 * P + o] = S(f[6]);
-        buf[5 * P + o] = S(f[7]);
-        buf[6 * P + o] = S(f[8]);
-        buf[9 * P + o] = S(g[0]);
-        buf[12 * P + o] = S(g[1]);
-        buf[13 * P + o] = S(g[2]);
-        buf[10 * P + o] = S(g[3]);
-        buf[11 * P + o] = S(g[4]);
+        const unsigned o = r0 + xx;
+        // f+_i goes to plane opp(i)
+        const int opp9[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+        const int opp5[5] = {0, 3, 4, 1, 2};
+#pragma unroll
+        for (int i = 0; i < 9; ++i) plane(buf, opp9[i], P)[o] = S(f[i]);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) plane(buf, 9 + opp5[i], P)[o] = S(g[i]);
     } else {
         const bool okE = !(G.wallE && x == G.nx - 1), okW = !(G.wallW && x == 0);
         const bool okN = !(G.wallN && y == G.ny - 1), okS = !(G.wallS && y == 0);
-        const int xm = (x == 0) ? G.nx - 1 : x - 1;
-        const int xp = (x == G.nx - 1) ? 0 : x + 1;
-        const int rm = ((y == 0) ? G.ny - 1 : y - 1) * G.pitch;
-        const int rp = ((y == G.ny - 1) ? 0 : y + 1) * G.pitch;
-        buf[0 * P + r0 + x] = S(f[0]);
-        buf[9 * P + r0 + x] = S(g[0]);
+        const unsigned xm = (x == 0) ? G.nx - 1 : x - 1;
+        const unsigned xp = (x == G.nx - 1) ? 0 : x + 1;
+        const unsigned rm = unsigned((y == 0) ? G.ny - 1 : y - 1) * unsigned(G.pitch);
+        const unsigned rp = unsigned((y == G.ny - 1) ? 0 : y + 1) * unsigned(G.pitch);
+        plane(buf, 0, P)[r0 + xx] = S(f[0]);
+        plane(buf, 9, P)[r0 + xx] = S(g[0]);
         if (okE) {
-            buf[1 * P + r0 + xp] = S(f[1]);
-            buf[10 * P + r0 + xp] = S(g[1]);
+            plane(buf, 1, P)[r0 + xp] = S(f[1]);
+            plane(buf, 10, P)[r0 + xp] = S(g[1]);
         }
         if (okN) {
-            buf[2 * P + rp + x] = S(f[2]);
-            buf[11 * P + rp + x] = S(g[2]);
+            plane(buf, 2, P)[rp + xx] = S(f[2]);
+            plane(buf, 11, P)[rp + xx] = S(g[2]);
         }
         if (okW) {
-            buf[3 * P + r0 + xm] = S(f[3]);
-            buf[12 * P + r0 + xm] = S(g[3]);
+            plane(buf, 3, P)[r0 + xm] = S(f[3]);
+            plane(buf, 12, P)[r0 + xm] = S(g[3]);
         }
         if (okS) {
-            buf[4 * P + rm + x] = S(f[4]);
-            buf[13 * P + rm + x] = S(g[4]);
+            plane(buf, 4, P)[rm + xx] = S(f[4]);
+            plane(buf, 13, P)[rm + xx] = S(g[4]);
         }
-        if (okE && okN) buf[5 * P + rp + xp] = S(f[5]);
-        if (okW && okN) buf[6 * P + rp + xm] = S(f[6]);
-        if (okW && okS) buf[7 * P + rm + xm] = S(f[7]);
-        if (okE && okS) buf[8 * P + rm + xp] = S(f[8]);
+        if (okE && okN) plane(buf, 5, P)[rp + xp] = S(f[5]);
+        if (okW && okN) plane(buf, 6, P)[rp + xm] = S(f[6]);
+        if (okW && okS) plane(buf, 7, P)[rm + xm] = S(f[7]);
+        if (okE && okS) plane(buf, 8, P)[rm + xp] = S(f[8]);
     }
 }
 

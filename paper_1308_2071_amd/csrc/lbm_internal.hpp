@@ -17,6 +17,19 @@ constexpr int kPitchAlign = 64;  // row pitch in elements
 template <typename S, typename R>
 hipError_t launch_step(const void* src, void* dst, const void* med, const Geo& G,
                        const Phys<R>& P, hipStream_t s);
+// Queries the device once for the two-step kernel's launch shape (call outside graph capture)
+template <typename S, typename R>
+void prepare_tb2();
+// Whether two steps per launch are faster than one for this grid and these types
+template <typename S, typename R>
+bool tb2_pays(const Geo& G, bool per_node_medium);
+// Rows per segment and work-groups per launch of the two-step kernel
+template <typename S, typename R>
+void tb2_shape(const Geo& G, bool per_node_medium, int* rows, int* nwg);
+// Two pull-layout steps in one launch, src (step n) to dst (step n + 2)
+template <typename S, typename R>
+hipError_t launch_tb2_step(const void* src, void* dst, const void* med, const Geo& G,
+                           const Phys<R>& P, hipStream_t s);
 // AA-pattern step in place; parity 0: the state is in the kAAOpp form, 1: kAAOwn
 template <typename S, typename R>
 hipError_t launch_aa_step(void* buf, const void* med, const Geo& G, const Phys<R>& P,

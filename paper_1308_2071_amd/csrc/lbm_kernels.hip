@@ -26,12 +26,13 @@ __global__ __launch_bounds__(kTileX) void step_kernel(const S* __restrict__ src,
     Med<R> md;
     node_state<R, PN, S>(src, med, G, P, x, y, f, g, m, md);
     collide<R>(f, g, m, md, P);
-    const int o = y * G.pitch + x;
+    const unsigned o = (unsigned(y) * unsigned(G.pitch) + unsigned(x)) * unsigned(sizeof(S));
 #pragma unroll
-    for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(S(f[i]), dst + i * G.plane + o);
+    for (int i = 0; i < 9; ++i)
+        __builtin_nontemporal_store(S(f[i]), &at(plane(dst, i, G.plane), o));
 #pragma unroll
     for (int i = 0; i < 5; ++i)
-        __builtin_nontemporal_store(S(g[i]), dst + (9 + i) * G.plane + o);
+        __builtin_nontemporal_store(S(g[i]), &at(plane(dst, 9 + i, G.plane), o));
 }
 
 // One AA-pattern time step in place (layout L = kAAOpp or kAAOwn read, the other written).
@@ -54,33 +55,225 @@ __global__ __launch_bounds__(kTileX) void aa_step_kernel(S* __restrict__ buf,
     pull<R, S, L>(buf, G, x, y, f, g);
     const Med<R> md = load_medium<R, PN, S>(med, y * G.pitch + x, G.plane, P);
     const Mac<R> m = fluid_macros<R>(f, g, md, P);
-    const bool nearW = G.wallW && x == 1, nearE = G.wallE && x == G.nx - 2;
-    const bool nearS = G.wallS && y == 1, nearN = G.wallN && y == G.ny - 2;
-    if (nearW || nearE || nearS || nearN) {
-        // up to three wall nodes (two sides and their corner) have (x, y) as inward neighbour
-        const int dxs[8] = {-1, 1, 0, 0, -1, 1, -1, 1};
-        const int dys[8] = {0, 0, -1, 1, -1, -1, 1, 1};
-        for (int k = 0; k < 8; ++k) {
-            const int xb = x + dxs[k], yb = y + dys[k];
-            if (xb < 0 || xb >= G.nx || yb < 0 || yb >= G.ny) continue;
-            const bool bW = G.wallW && xb == 0, bE = G.wallE && xb == G.nx - 1;
-            const bool bS = G.wallS && yb == 0, bN = G.wallN && yb == G.ny - 1;
-            if (!(bW || bE || bS || bN)) continue;
-            if (xb + (bW ? 1 : 0) - (bE ? 1 : 0) != x || yb + (bS ? 1 : 0) - (bN ? 1 : 0) != y)
-                continue;
-            R fb[9], gb[5];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) fb[i] = f[i];
-#pragma unroll
-            for (int i = 0; i < 5; ++i) gb[i] = g[i];
-            const Med<R> mdb = load_medium<R, PN, S>(med, yb * G.pitch + xb, G.plane, P);
-            const Mac<R> mb = wall_state<R>(bW, bE, bS, bN, fb, gb, m, md, mdb, P);
-            collide<R>(fb, gb, mb, mdb, P);
-            aa_store<S, R, L>(buf, G, xb, yb, fb, gb);
-        }
-    }
+    step_wall_neighbours<R, PN, S>(med, G, P, x, y, f, g, m, md,
+                                   [&](int xb, int yb, const R* fb, const R* gb) {
+                                       aa_store<S, R, L>(buf, G, xb, yb, fb, gb);
+                                   });
     collide<R>(f, g, m, md, P);
     aa_store<S, R, L>(buf, G, x, y, f, g);
+}
+
+// Two time steps per launch (temporal blocking), pull layout, bitwise equal to two launches of
+// step_kernel.  Each wavefront owns a strip of kTbCols columns and sweeps a segment of rows.
+// Lane l computes the intermediate step n+1 at column x0 - 1 + l (the strip plus one column
+// on each side) for each row, straight from the step-n buffer, and keeps three consecutive
+// rows of it in registers, rounded to the storage type as a store would round them.  Step n+2
+// at row y then gathers its populations from those registers: from its own lane and, across
+// lanes, from its left and right neighbours.  A wall node is stepped by its inward
+// neighbour's lane, which holds the populations its reconstruction needs.  Per two steps each
+// node's populations cross HBM once each way, against twice for two single steps.
+constexpr int kTbCols = 62;
+constexpr int kTbWaves = 4;     // strips (wavefronts) per work-group
+constexpr int kTbRounds = 6;    // aim: the work-groups fill about this many resident sets
+constexpr int kTbMinRows = 8;
+
+// Raw inputs of the intermediate step at one node, loaded one row ahead of their use so that
+// the loads are in flight while the previous row computes: the populations pulled at the node
+// (its inward neighbour for a wall node) and the medium there and at the node itself.
+template <typename S>
+struct TbRaw {
+    S f[9], g[5];
+    S phi_f, K_f;   // medium where the populations are pulled
+    S phi, K;       // medium at the node
+};
+
+template <typename S, bool PN>
+__device__ __forceinline__ void tb_load(const S* __restrict__ src, const S* __restrict__ med,
+                                        const Geo& G, int x, bool ok, int r, TbRaw<S>& raw) {
+    // every field is assigned on every path (a field set on one branch only would keep the
+    // struct in scratch memory)
+    S phi_f = S(1), K_f = S(1), phi = S(1), K = S(1);
+    if (ok) {
+        const bool onW = G.wallW && x == 0, onE = G.wallE && x == G.nx - 1;
+        const bool onS = G.wallS && r == 0, onN = G.wallN && r == G.ny - 1;
+        const int xf = x + (onW ? 1 : 0) - (onE ? 1 : 0);
+        const int yf = r + (onS ? 1 : 0) - (onN ? 1 : 0);
+        pull<S, S>(src, G, xf, yf, raw.f, raw.g);
+        if constexpr (PN) {
+            constexpr unsigned B = sizeof(S);
+            const unsigned of = (unsigned(yf) * unsigned(G.pitch) + unsigned(xf)) * B;
+            const unsigned o = (unsigned(r) * unsigned(G.pitch) + unsigned(x)) * B;
+            phi_f = at(med, of);
+            K_f = at(plane(med, 1, G.plane), of);
+            phi = at(med, o);
+            K = at(plane(med, 1, G.plane), o);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) raw.f[i] = S(0);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) raw.g[i] = S(0);
+    }
+    raw.phi_f = phi_f;
+    raw.K_f = K_f;
+    raw.phi = phi;
+    raw.K = K;
+}
+
+// The intermediate step at (x, r) from its raw inputs: node_state's arithmetic, then collide,
+// rounded to the storage type.
+template <typename S, typename R, bool PN>
+__device__ __forceinline__ void tb_finish(const TbRaw<S>& raw, const Geo& G, const Phys<R>& P,
+                                          int x, bool ok, int r, S out[14]) {
+    if (!ok) {
+#pragma unroll
+        for (int i = 0; i < 14; ++i) out[i] = S(0);
+        return;
+    }
+    R f[9], g[5];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = R(raw.f[i]);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) g[i] = R(raw.g[i]);
+    const bool onW = G.wallW && x == 0, onE = G.wallE && x == G.nx - 1;
+    const bool onS = G.wallS && r == 0, onN = G.wallN && r == G.ny - 1;
+    Med<R> md;
+    Mac<R> m;
+    if constexpr (PN)
+        md = medium_from<R>(R(raw.phi), R(raw.K), P);
+    else
+        md = Med<R>{P.phi, P.inv_phi, P.c_lin, P.c_nl};
+    if (!(onW || onE || onS || onN)) {
+        m = fluid_macros<R>(f, g, md, P);
+    } else {
+        Med<R> mdf = md;
+        if constexpr (PN) mdf = medium_from<R>(R(raw.phi_f), R(raw.K_f), P);
+        const Mac<R> mf = fluid_macros<R>(f, g, mdf, P);
+        m = wall_state<R>(onW, onE, onS, onN, f, g, mf, mdf, md, P);
+    }
+    collide<R>(f, g, m, md, P);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) out[i] = S(f[i]);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) out[9 + i] = S(g[i]);
+}
+
+// Row r of the intermediate step as seen from this lane: wrapped on a periodic axis, absent
+// beyond a walled side.
+__device__ __forceinline__ bool tb_rowc(const Geo& G, bool col_ok, int& r) {
+    if (r >= 0 && r < G.ny) return col_ok;
+    if (G.wallS) return false;
+    r = r < 0 ? r + G.ny : r - G.ny;
+    return col_ok;
+}
+
+template <typename S, typename R, bool PN>
+__global__ __launch_bounds__(64 * kTbWaves) void tb2_step_kernel(const S* __restrict__ src,
+                                                                 S* __restrict__ dst,
+                                                                 const S* __restrict__ med,
+                                                                 Geo G, Phys<R> P, int nstrips,
+                                                                 int rows) {
+    const int lane = threadIdx.x & 63;
+    // A work-group holds kTbWaves adjacent strips of one row segment, kept in step by a
+    // barrier per row, so that the cache lines the neighbouring strips share are used while
+    // resident.  Every wavefront runs the same rows; one past the last strip loads and stores
+    // nothing.  Work-groups are dealt round-robin over the 8 XCDs; each XCD is given a
+    // contiguous range of the logical work-groups (a bijection), so that neighbouring strips
+    // and segments share its L2.
+    int wg = blockIdx.x;
+    {
+        const int n = gridDim.x, per = n / 8, extra = n % 8;
+        const int xcd = wg % 8, slot = wg / 8;
+        wg = xcd * per + min(xcd, extra) + slot;
+    }
+    const int ngrp = (nstrips + kTbWaves - 1) / kTbWaves;
+    const int strip = (wg % ngrp) * kTbWaves + (threadIdx.x >> 6), seg = wg / ngrp;
+    const bool active = strip < nstrips;
+    const int x0 = strip * kTbCols;
+    // this lane's column; outside a walled side it computes nothing
+    int x = x0 - 1 + lane;
+    bool col_ok = active;
+    if (x < 0 || x >= G.nx) {
+        col_ok = active && !G.wallW;
+        x = x < 0 ? x + G.nx : x - G.nx;
+        if (x < 0 || x >= G.nx) x = 0;  // only reached by an idle wavefront
+    }
+    // lanes 1..kTbCols write step n+2 at their column
+    const bool out_lane = active && lane >= 1 && lane <= kTbCols && x0 - 1 + lane < G.nx;
+    const int y0 = seg * rows;
+    const int y1 = min(y0 + rows, G.ny);
+    S a[14], b[14], c[14];  // step n+1 at rows y-1, y, y+1 of this lane's column
+    S phib = S(1), Kb = S(1), phic = S(1), Kc = S(1);  // medium at (x, y) and (x, y + 1)
+    TbRaw<S> raw;
+    {
+        int r = y0 - 1;
+        bool ok = tb_rowc(G, col_ok, r);
+        tb_load<S, PN>(src, med, G, x, ok, r, raw);
+        tb_finish<S, R, PN>(raw, G, P, x, ok, r, a);
+        r = y0;
+        ok = tb_rowc(G, col_ok, r);
+        tb_load<S, PN>(src, med, G, x, ok, r, raw);
+        tb_finish<S, R, PN>(raw, G, P, x, ok, r, b);
+        phib = raw.phi;
+        Kb = raw.K;
+        r = y0 + 1;
+        ok = tb_rowc(G, col_ok, r);
+        tb_load<S, PN>(src, med, G, x, ok, r, raw);
+    }
+    for (int y = y0; y < y1; ++y) {
+        {
+            int r = y + 1;
+            const bool ok = tb_rowc(G, col_ok, r);
+            tb_finish<S, R, PN>(raw, G, P, x, ok, r, c);
+            phic = raw.phi;
+            Kc = raw.K;
+            r = y + 2;  // issue the next row's loads now; they complete during this row's work
+            const bool ok2 = tb_rowc(G, col_ok, r);
+            tb_load<S, PN>(src, med, G, x, ok2, r, raw);
+        }
+        // gather step n+1 populations arriving at (x, y): f_i from (x - ex_i, y - ey_i)
+        const S f1 = __shfl_up(b[1], 1, 64), g1 = __shfl_up(b[10], 1, 64);
+        const S f5 = __shfl_up(a[5], 1, 64), f8 = __shfl_up(c[8], 1, 64);
+        const S f3 = __shfl_down(b[3], 1, 64), g3 = __shfl_down(b[12], 1, 64);
+        const S f6 = __shfl_down(a[6], 1, 64), f7 = __shfl_down(c[7], 1, 64);
+        const bool wall = (G.wallW && x == 0) || (G.wallE && x == G.nx - 1) ||
+                          (G.wallS && y == 0) || (G.wallN && y == G.ny - 1);
+        if (out_lane && !wall) {
+            R f[9] = {R(b[0]), R(f1), R(a[2]), R(f3), R(c[4]), R(f5), R(f6), R(f7), R(f8)};
+            R g[5] = {R(b[9]), R(g1), R(a[11]), R(g3), R(c[13])};
+            Med<R> md;
+            if constexpr (PN)
+                md = medium_from<R>(R(phib), R(Kb), P);
+            else
+                md = Med<R>{P.phi, P.inv_phi, P.c_lin, P.c_nl};
+            const Mac<R> m = fluid_macros<R>(f, g, md, P);
+            step_wall_neighbours<R, PN, S>(
+                med, G, P, x, y, f, g, m, md, [&](int xb, int yb, const R* fb, const R* gb) {
+                    const unsigned ob = unsigned(yb) * unsigned(G.pitch) + unsigned(xb);
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) plane(dst, i, G.plane)[ob] = S(fb[i]);
+#pragma unroll
+                    for (int i = 0; i < 5; ++i) plane(dst, 9 + i, G.plane)[ob] = S(gb[i]);
+                });
+            collide<R>(f, g, m, md, P);
+            const unsigned o =
+                (unsigned(y) * unsigned(G.pitch) + unsigned(x)) * unsigned(sizeof(S));
+            // plain stores: a strip's edge lines are shared with its neighbour, and merge in
+            // L2 before they go to HBM (non-temporal stores cost 10 % here)
+#pragma unroll
+            for (int i = 0; i < 9; ++i) at(plane(dst, i, G.plane), o) = S(f[i]);
+#pragma unroll
+            for (int i = 0; i < 5; ++i) at(plane(dst, 9 + i, G.plane), o) = S(g[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < 14; ++i) {
+            a[i] = b[i];
+            b[i] = c[i];
+        }
+        phib = phic;
+        Kb = Kc;
+        __syncthreads();
+    }
 }
 
 // Wave-level reductions over the 64 lanes of a wavefront.
@@ -289,6 +482,83 @@ hipError_t launch_step(const void* src, void* dst, const void* med, const Geo& G
     return hipGetLastError();
 }
 
+
+// Work-groups of the two-step kernel resident on the device at once (0 if unknown).
+template <typename S, typename R, bool PN>
+int tb_resident_groups() {
+    static const int n = [] {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tb2_step_kernel<S, R, PN>,
+                                                         64 * kTbWaves, 0) != hipSuccess)
+            return 0;
+        return cus * per_cu;
+    }();
+    return n;
+}
+
+// Rows per segment of the two-step kernel.  Long segments amortise the two halo rows of the
+// intermediate step; short-lived work-groups let vertically neighbouring segments run close
+// together in time and keep the tail of the launch short.  Measured on the 4096^2 workload:
+// about 6 rounds of the resident set (12 rows) is best, 1 round (69 rows) is 10 % slower.
+int tb_rows(const Geo& G, int nstrips, int resident) {
+    const int ngrp = (nstrips + kTbWaves - 1) / kTbWaves;
+    const int nseg = resident > 0 ? max(1, kTbRounds * resident / ngrp) : 1;
+    return max(kTbMinRows, (G.ny + nseg - 1) / nseg);
+}
+
+template <typename S, typename R>
+int tb_resident(bool per_node_medium) {
+    return per_node_medium ? tb_resident_groups<S, R, true>()
+                           : tb_resident_groups<S, R, false>();
+}
+
+// Queries the resident set of the two-step kernel once, outside any graph capture.
+template <typename S, typename R>
+void prepare_tb2() {
+    (void)tb_resident<S, R>(true);
+    (void)tb_resident<S, R>(false);
+}
+
+// Whether two steps per launch beat one: only with equal storage and arithmetic types (with
+// FP64 arithmetic on FP32 storage the kernel holds 190 registers and runs at 2 waves per SIMD,
+// 20 % slower than single steps) and with work-groups for at least a quarter of the resident
+// set at 16-row segments (measured: 1024^2 gains 4 % in FP32 and 23 % in FP64, 4096^2 31 % and
+// 35 %; on 256^2 the few long row loops are latency-bound and run 4x slower fused).
+template <typename S, typename R>
+bool tb2_pays(const Geo& G, bool per_node_medium) {
+    if (!std::is_same<S, R>::value) return false;
+    const int resident = tb_resident<S, R>(per_node_medium);
+    const int nstrips = (G.nx + kTbCols - 1) / kTbCols;
+    const long long groups =
+        (long long)((nstrips + kTbWaves - 1) / kTbWaves) * ((G.ny + 15) / 16);
+    return resident > 0 && 4 * groups >= resident;
+}
+
+template <typename S, typename R>
+void tb2_shape(const Geo& G, bool per_node_medium, int* rows, int* nwg) {
+    const int nstrips = (G.nx + kTbCols - 1) / kTbCols;
+    *rows = tb_rows(G, nstrips, tb_resident<S, R>(per_node_medium));
+    *nwg = (nstrips + kTbWaves - 1) / kTbWaves * ((G.ny + *rows - 1) / *rows);
+}
+
+template <typename S, typename R>
+hipError_t launch_tb2_step(const void* src, void* dst, const void* med, const Geo& G,
+                           const Phys<R>& P, hipStream_t s) {
+    const int nstrips = (G.nx + kTbCols - 1) / kTbCols;
+    int rows = 0, nwg = 0;
+    tb2_shape<S, R>(G, med != nullptr, &rows, &nwg);
+    if (med)
+        tb2_step_kernel<S, R, true><<<nwg, 64 * kTbWaves, 0, s>>>(
+            (const S*)src, (S*)dst, (const S*)med, G, P, nstrips, rows);
+    else
+        tb2_step_kernel<S, R, false><<<nwg, 64 * kTbWaves, 0, s>>>((const S*)src, (S*)dst,
+                                                                   nullptr, G, P, nstrips, rows);
+    return hipGetLastError();
+}
+
 // parity 0: the state is in the kAAOpp form (even step count); 1: kAAOwn (odd)
 template <typename S, typename R>
 hipError_t launch_aa_step(void* buf, const void* med, const Geo& G, const Phys<R>& P,
@@ -387,6 +657,11 @@ hipError_t launch_pitch_copy(void* dst, const void* src, const Geo& G, double v,
                                           const Phys<R>&, hipStream_t);                          \
     template hipError_t launch_aa_step<S, R>(void*, const void*, const Geo&, const Phys<R>&,     \
                                              int, hipStream_t);                                  \
+    template hipError_t launch_tb2_step<S, R>(const void*, void*, const void*, const Geo&,       \
+                                              const Phys<R>&, hipStream_t);                      \
+    template void prepare_tb2<S, R>();                                                           \
+    template bool tb2_pays<S, R>(const Geo&, bool);                                              \
+    template void tb2_shape<S, R>(const Geo&, bool, int*, int*);                                 \
     template hipError_t launch_observe<S, R>(const void*, const void*, const Geo&,               \
                                              const Phys<R>&, int, void*, void*, void*, void*,    \
                                              double*, int, double, double*, hipStream_t);        \

@@ -144,6 +144,7 @@ def test_aa_layout_halves_the_state_memory(lbm):
 
 def test_aa_layout_limits(lbm):
     assert status_of(lbm, layout=3) == -1                          # LBM_E_INVAL
+    assert status_of(lbm, steps_per_launch=3) == -1
     assert status_of(lbm, layout=1, checkpoint_every=10) == -6     # LBM_E_UNSUPPORTED: no tape
     from paper_1308_2071_amd import _abi
     p = (_abi.LbmParams * 1)(lbm.make_params(nx=16, ny=16, layout="aa"))
