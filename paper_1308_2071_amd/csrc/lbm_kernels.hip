@@ -1,5 +1,6 @@
-// lbm_kernels.hip -- plain (single cavity) kernels: the fused time step, the observables
-// pass, the wall Nusselt reduction and state initialisation.
+// lbm_kernels.hip -- single-cavity kernels: the time step (one step per launch, two steps per
+// launch, and the in-place AA-layout forms), the observables pass, the wall Nusselt reduction,
+// the stream function and state initialisation.
 #include "lbm_device.hpp"
 #include "lbm_internal.hpp"
 
@@ -71,7 +72,8 @@ __global__ __launch_bounds__(kTileX) void aa_step_kernel(S* __restrict__ buf,
 // at row y then gathers its populations from those registers: from its own lane and, across
 // lanes, from its left and right neighbours.  A wall node is stepped by its inward
 // neighbour's lane, which holds the populations its reconstruction needs.  Per two steps each
-// node's populations cross HBM once each way, against twice for two single steps.
+// node's populations cross HBM about once each way (plus the halo of the intermediate step),
+// against twice for two single steps.
 constexpr int kTbCols = 62;
 constexpr int kTbWaves = 4;     // strips (wavefronts) per work-group
 constexpr int kTbRounds = 6;    // aim: the work-groups fill about this many resident sets

@@ -113,8 +113,9 @@ def test_batch_rejects_mixed_dtypes_and_tapes():
 
 
 def test_batch64_workload_runs_and_matches_plain_on_sampled_cavities(tmp_path):
-    """The 64-cavity workload at its full size for a few hundred steps: every cavity stays finite
-    and seven cavities (one per side length) equal their plain runs bitwise."""
+    """The 64-cavity workload at its full size for a few hundred steps: every cavity stays finite,
+    and seven cavities (one per side length) equal their plain runs bitwise and the FP64 oracle
+    within 1e-4 of each field's range (p up to a constant) and Nu within 1e-3."""
     cav = workloads.batch64()
     params = [dict(c["params"], dtype="fp32") for c in cav]
     phis = [c["phi"] for c in cav]
@@ -133,3 +134,16 @@ def test_batch64_workload_runs_and_matches_plain_on_sampled_cavities(tmp_path):
         for k in FIELDS:
             assert torch.equal(g[k], r[k]), (nx, k)
         c.close()
+        p = {k: v for k, v in params[i].items() if k != "dtype"}
+        ref.set_threads(len(os.sched_getaffinity(0)))
+        lat = ref.RefLattice(phi_uniform=float(np.float32(phis[i])), **p)
+        lat.step(300)
+        o = lat.observables(dynamic_pressure=True)
+        lat.close()
+        for k in FIELDS:
+            d = g[k].double().cpu().numpy() - o[k]
+            if k == "p":
+                d = d - d.mean()     # the free pressure level
+            rng = max(o[k].max() - o[k].min(), 1e-2 * np.abs(o[k]).max())
+            assert np.abs(d).max() <= 1e-4 * rng, (nx, k, np.abs(d).max() / rng)
+        assert abs(obs[i]["nu_hot"] - o["nu_hot"]) <= 1e-3, (nx, obs[i]["nu_hot"], o["nu_hot"])
