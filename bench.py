@@ -40,7 +40,8 @@ TRAFFIC_PROFILES = {
     "step_kernel<float,float,true>": os.path.join(ROOT, "profiles",
                                                   "step_kernel_fp32_4096_traffic.md"),
 }
-STEP_SOURCES = ("paper_1308_2071_amd/csrc/lbm_device.hpp", "paper_1308_2071_amd/csrc/lbm_kernels.hip",
+STEP_SOURCES = ("paper_1308_2071_amd/csrc/lbm_device.hpp", "paper_1308_2071_amd/csrc/lbm_tb2.hpp",
+                "paper_1308_2071_amd/csrc/lbm_kernels.hip",
                 "paper_1308_2071_amd/build.py")
 
 
@@ -158,7 +159,9 @@ def leg_batched(torch, steps=1000):
                              2),
             "bytes_per_node": BYTES_PER_NODE_FP32_UNIFORM,
             "shape": {"nodes_per_item": shape[0], "wg": shape[1], "wgs": shape[2],
-                      "graph_steps": shape[3]},
+                      "graph_steps": shape[3], "steps_per_launch": shape[4],
+                      "rows_per_segment": shape[5], "two_step_wgs": shape[6],
+                      "two_step_strips_per_wg": shape[7]},
             "plain_64_launches_per_step_mlups": round(seq, 1),
             "plain_per_cavity_graph_mlups": round(own, 1),
             "speedup_vs_64_launches": round(mlups / seq, 2),

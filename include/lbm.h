@@ -201,7 +201,10 @@ lbm_status lbm_destroy(lbm_ctx* c);
 lbm_status lbm_batch_workspace_size(int32_t n, const lbm_params* p, size_t* bytes);
 
 /* Create a batch of n cavities.  tune_cache_path: file where the launch shape picked by the
- * autotuner is cached per (device, dtype, cavity set); NULL disables tuning (default shape). */
+ * autotuner is cached per (device, dtype, cavity set); NULL disables tuning (default shape).
+ * The autotuner also times two steps per launch and keeps it where it is faster;
+ * p[0].steps_per_launch = 1 or 2 forces one or two (the other cavities' values are ignored).
+ * Results are bitwise the same either way. */
 lbm_status lbm_batch_init(lbm_ctx** out, int32_t n, const lbm_params* p,
                           const double* phi_uniform, void* workspace, size_t ws_bytes,
                           void* hip_stream, const char* tune_cache_path);
@@ -216,8 +219,11 @@ lbm_status lbm_batch_observables(lbm_ctx* c, lbm_obs* o);
  * arrays [ny_i][nx_i] of the batch's dtype, as in lbm_observables. */
 lbm_status lbm_batch_fields(lbm_ctx* c, int32_t i, void* ux, void* uy, void* p, void* T);
 
-/* Launch shape in use: out[0] nodes per work-item along x, out[1] work-group size,
- * out[2] work-groups per step, out[3] steps per graph replay. */
+/* Launch shape in use (out holds 8 entries): out[0] nodes per work-item along x, out[1]
+ * work-group size, out[2] work-groups per step of the one-step kernel, out[3] steps per graph
+ * replay, out[4] time steps per launch (2 when the autotuner, or steps_per_launch = 2 of the
+ * first cavity, chose the two-step kernel), out[5] its rows per segment (0 if unused), out[6]
+ * its work-groups per launch, out[7] its strips (wavefronts) per work-group. */
 lbm_status lbm_batch_shape(const lbm_ctx* c, int32_t* out);
 
 /* Human-readable name of a status code. */

@@ -147,7 +147,7 @@ def lbm_batch_fields(ctx: int, i: int, ux=None, uy=None, p=None, T=None) -> None
 
 
 def lbm_batch_shape(ctx: int):
-    out = (C.c_int32 * 4)()
+    out = (C.c_int32 * 8)()
     check(library().lbm_batch_shape(ctx, out), "lbm_batch_shape")
     return tuple(out)
 

@@ -266,6 +266,9 @@ struct lbm_ctx {
     size_t b_state_bytes = 0, b_off_buf[2] = {0, 0}, b_off_cav = 0, b_off_phys = 0;
     size_t b_off_tiles = 0, b_off_part = 0, b_max_tiles = 0;
     int b_wg = 4, b_npt = 1, b_nwg = 0, b_ntiles = 0;   // b_wg: rows per tile
+    // two steps per launch: rows per segment (0: one step per launch) and work-groups
+    size_t b_off_cav2 = 0, b_off_tbwg = 0, b_max_tbwg = 0;
+    int b_tb_rows = 0, b_tb_nwg = 0, b_tb_waves = 4;
 
     void* buf(int i) const { return ws + L.off_buf[i]; }
     void* medp() const { return med ? ws + L.off_med : nullptr; }
@@ -413,7 +416,19 @@ constexpr int kMinTileWidth = 64;      // narrowest tile of any supported launch
 struct BatchLayout {
     std::vector<long long> off;
     size_t state_bytes, off_buf[2], off_cav, off_phys, off_tiles, off_part, max_tiles, total;
+    size_t off_cav2, off_tbwg, max_tbwg;   // tables of the two-step form
 };
+
+// Work-groups of the batched two-step kernel for segments of `rows` rows, `waves` strips per
+// work-group.
+size_t batch_tb_groups(const std::vector<Geo>& G, int rows, int waves) {
+    size_t n = 0;
+    for (const Geo& g : G) {
+        const size_t strips = size_t((g.nx + kTbCols - 1) / kTbCols);
+        n += (strips + waves - 1) / waves * size_t((g.ny + rows - 1) / rows);
+    }
+    return n;
+}
 
 lbm_status batch_layout(int32_t n, const lbm_params* p, BatchLayout* L) {
     if (n <= 0) return fail(LBM_E_INVAL, "batch of %d cavities", n);
@@ -452,6 +467,13 @@ lbm_status batch_layout(int32_t n, const lbm_params* p, BatchLayout* L) {
     L->off_tiles = o;
     L->max_tiles = tiles;
     o += align_up(tiles * sizeof(int));
+    std::vector<Geo> geos;
+    for (int i = 0; i < n; ++i) geos.push_back(make_geo(p[i]));
+    L->off_cav2 = o;
+    o += align_up(n * sizeof(BatchCavity));
+    L->off_tbwg = o;
+    L->max_tbwg = batch_tb_groups(geos, kTbMinRows, 1);   // the most: shortest rows, 1 strip
+    o += align_up(L->max_tbwg * sizeof(int));
     L->off_part = o;
     o += align_up(size_t(n) * (3 * kBatchObsWG + 8) * sizeof(double));
     L->total = o;
@@ -510,6 +532,52 @@ BatchTable<R> batch_table(const lbm_ctx* c) {
     return T;
 }
 
+// Tables of the two-step form for segments of `rows` rows and `waves` strips per work-group:
+// per cavity its first logical work-group (tile0) and strip groups (tiles_x), and the
+// work-group -> cavity list.
+hipError_t batch_tb_tables(lbm_ctx* c, int rows, int waves) {
+    std::vector<BatchCavity> cav(c->ncav);
+    std::vector<int> wc;
+    for (int i = 0; i < c->ncav; ++i) {
+        const Geo& G = c->bG[i];
+        const int ngrp = ((G.nx + kTbCols - 1) / kTbCols + waves - 1) / waves;
+        cav[i].G = G;
+        cav[i].off = c->boff[i];
+        cav[i].tile0 = int(wc.size());
+        cav[i].tiles_x = ngrp;
+        wc.insert(wc.end(), size_t(ngrp) * size_t((G.ny + rows - 1) / rows), i);
+    }
+    if (rows < kTbMinRows || wc.size() > c->b_max_tbwg) return hipErrorInvalidValue;
+    c->b_tb_nwg = int(wc.size());
+    hipError_t e = hipMemcpy(c->ws + c->b_off_cav2, cav.data(), cav.size() * sizeof(BatchCavity),
+                             hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+    return hipMemcpy(c->ws + c->b_off_tbwg, wc.data(), wc.size() * sizeof(int),
+                     hipMemcpyHostToDevice);
+}
+
+template <typename R>
+BatchTable<R> batch_tb_table(const lbm_ctx* c) {
+    BatchTable<R> T;
+    T.cav = (const BatchCavity*)(c->ws + c->b_off_cav2);
+    T.phys = (const Phys<R>*)(c->ws + c->b_off_phys);
+    T.tile_cav = (const int*)(c->ws + c->b_off_tbwg);
+    T.ncav = c->ncav;
+    T.ntiles = c->b_tb_nwg;
+    return T;
+}
+
+// Two steps of every cavity in one launch, from buffer `from` to the other.
+hipError_t batch_step2(lbm_ctx* c, int from, hipStream_t s) {
+    const void* src = c->ws + c->b_off_buf[from];
+    void* dst = c->ws + c->b_off_buf[1 - from];
+    return with_types(c->p.dtype, [&](auto st, auto rt) {
+        LBM_TYPES(st, rt)
+        return launch_batch_tb2<S, R>(src, dst, batch_tb_table<R>(c), c->b_tb_rows,
+                                      c->b_tb_waves, s);
+    });
+}
+
 hipError_t batch_step_once(lbm_ctx* c, int from, hipStream_t s) {
     const void* src = c->ws + c->b_off_buf[from];
     void* dst = c->ws + c->b_off_buf[1 - from];
@@ -526,9 +594,17 @@ lbm_status ensure_batch_graph(lbm_ctx* c, int start) {
     HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal), "begin capture");
     hipError_t err = hipSuccess;
     int b = start;
-    for (int k = 0; k < kBatchGraphSteps && err == hipSuccess; ++k) {
-        err = batch_step_once(c, b, c->cap);
-        b = 1 - b;
+    if (c->b_tb_rows > 0) {
+        // kBatchGraphSteps / 2 two-step launches: an even number of buffer swaps
+        for (int k = 0; k < kBatchGraphSteps / 2 && err == hipSuccess; ++k) {
+            err = batch_step2(c, b, c->cap);
+            b = 1 - b;
+        }
+    } else {
+        for (int k = 0; k < kBatchGraphSteps && err == hipSuccess; ++k) {
+            err = batch_step_once(c, b, c->cap);
+            b = 1 - b;
+        }
     }
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(c->cap, &graph);
@@ -568,52 +644,87 @@ std::string batch_key(const lbm_ctx* c) {
         mix(uint64_t(G.ny));
     }
     char buf[128];
-    snprintf(buf, sizeof buf, "%s|%s|%016llx", arch.c_str(),
+    snprintf(buf, sizeof buf, "v3|%s|%s|%016llx", arch.c_str(),
              c->p.dtype == LBM_FP64 ? "fp64" : c->p.dtype == LBM_FP32_F64 ? "fp32_f64" : "fp32",
              (unsigned long long)h);
     return buf;
 }
 
-bool cache_lookup(const char* path, const std::string& key, int* wg, int* npt, int* nwg) {
+// A cache line: key, rows per tile, 64-node segments per work-item, work-groups (0: one tile
+// per work-group), rows per segment of the two-step form (0: one step per launch) and its
+// strips per work-group.
+bool cache_lookup(const char* path, const std::string& key, int* wg, int* npt, int* nwg,
+                  int* tb_rows, int* tb_waves) {
     FILE* f = std::fopen(path, "r");
     if (!f) return false;
-    char k[256];
-    int a, b, d;
+    char line[512], k[256];
+    int a, b, d, t, w;
     bool found = false;
-    while (std::fscanf(f, "%255s %d %d %d", k, &a, &b, &d) == 4)
-        if (key == k) {
+    while (std::fgets(line, sizeof line, f))
+        if (std::sscanf(line, "%255s %d %d %d %d %d", k, &a, &b, &d, &t, &w) == 6 && key == k) {
             *wg = a;
             *npt = b;
             *nwg = d;
+            *tb_rows = t;
+            *tb_waves = w;
             found = true;
         }
     std::fclose(f);
     return found;
 }
 
-void cache_store(const char* path, const std::string& key, int wg, int npt, int nwg) {
+void cache_store(const char* path, const std::string& key, int wg, int npt, int nwg,
+                 int tb_rows, int tb_waves) {
     FILE* f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s %d %d %d\n", key.c_str(), wg, npt, nwg);
+    std::fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), wg, npt, nwg, tb_rows, tb_waves);
     std::fclose(f);
 }
 
-// Autotuner: times every supported tile shape (rows per work-group x 64-node segments per
-// work-item) with one tile per work-group and with chunked persistent grids of 2..16
-// work-groups per CU, on the batch itself, and keeps the fastest.  The result is cached per
-// (device, dtype, cavity shapes) in tune_cache_path.
+// Times `launches` launches of `step` (alternating buffers) after 3 untimed ones; ms per step.
+template <class Step>
+hipError_t time_steps(lbm_ctx* c, hipEvent_t e0, hipEvent_t e1, int steps_per_launch,
+                      Step&& step, float* ms_per_step) {
+    hipError_t e = hipSuccess;
+    int from = 0;
+    for (int k = 0; k < 3 && e == hipSuccess; ++k, from = 1 - from) e = step(from);
+    if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+    for (int k = 0; k < 10 && e == hipSuccess; ++k, from = 1 - from) e = step(from);
+    if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    *ms_per_step = ms / float(10 * steps_per_launch);
+    return e;
+}
+
+// Autotuner, on the batch itself.  The one-step kernel: every supported tile shape (rows per
+// work-group x 64-node segments per work-item), with one tile per work-group and with chunked
+// persistent grids of 2..16 work-groups per CU.  The two-step kernel: segments of 8, 12, 16
+// and 24 rows with 1, 2 or 4 strips per work-group.  It keeps the fastest per step (the one-step shape is kept either way, for odd
+// step counts), unless steps_per_launch of the first cavity forces one or two steps per
+// launch.  The result is cached per (device, dtype, cavity shapes, that setting) in
+// tune_cache_path.
 lbm_status batch_tune(lbm_ctx* c, const char* path) {
     int cu = 256;
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
-    const std::string key = batch_key(c);
-    int rows, npt, nwg;
-    if (path && cache_lookup(path, key, &rows, &npt, &nwg)) {
+    const int spl = c->bp[0].steps_per_launch;
+    const std::string key = batch_key(c) + "|s" + std::to_string(spl);
+    int rows, npt, nwg, tbr, tbw;
+    c->b_tb_rows = 0;
+    c->b_tb_nwg = 0;
+    if (path && cache_lookup(path, key, &rows, &npt, &nwg, &tbr, &tbw)) {
         c->b_wg = rows;
         c->b_npt = npt;
         HIP_TRY(batch_tables(c, 64 * npt, rows), "tile tables");
         c->b_nwg = nwg > 0 ? nwg : c->b_ntiles;
+        if (tbr > 0) {
+            HIP_TRY(batch_tb_tables(c, tbr, tbw), "two-step tables");
+            c->b_tb_rows = tbr;
+            c->b_tb_waves = tbw;
+        }
         return LBM_OK;
     }
     if (!path) {
@@ -621,16 +732,23 @@ lbm_status batch_tune(lbm_ctx* c, const char* path) {
         c->b_npt = 1;
         HIP_TRY(batch_tables(c, 64, 4), "tile tables");
         c->b_nwg = c->b_ntiles;
+        if (spl == 2) {
+            HIP_TRY(batch_tb_tables(c, 12, 4), "two-step tables");
+            c->b_tb_rows = 12;
+            c->b_tb_waves = 4;
+        }
         return LBM_OK;
     }
     const int shapes[10][2] = {{1, 1}, {1, 2}, {1, 4}, {2, 1}, {2, 2}, {2, 4},
                                {4, 1}, {4, 2}, {4, 4}, {8, 1}};
     const int per_cu[5] = {0, 2, 4, 8, 16};  // 0: one tile per work-group
+    const int tb_rows[4] = {8, 12, 16, 24};
+    const int tb_waves[3] = {1, 2, 4};
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "event");
     HIP_TRY(hipEventCreate(&e1), "event");
-    float best = 1e30f;
-    int br = 4, bn = 1, bg = 0;
+    float best = 1e30f, best_tb = 1e30f;
+    int br = 4, bn = 1, bg = 0, btr = 0, btw = 4;
     lbm_status st = LBM_OK;
     for (const auto& sh : shapes) {
         hipError_t e = batch_tables(c, 64 * sh[1], sh[0]);
@@ -639,16 +757,9 @@ lbm_status batch_tune(lbm_ctx* c, const char* path) {
             c->b_wg = sh[0];
             c->b_npt = sh[1];
             c->b_nwg = pc == 0 ? c->b_ntiles : std::min(c->b_ntiles, pc * cu);
-            int from = 0;
-            for (int k = 0; k < 3 && e == hipSuccess; ++k, from = 1 - from)
-                e = batch_step_once(c, from, c->stream);
-            if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
-            for (int k = 0; k < 10 && e == hipSuccess; ++k, from = 1 - from)
-                e = batch_step_once(c, from, c->stream);
-            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            e = time_steps(c, e0, e1, 1, [&](int from) { return batch_step_once(c, from, c->stream); },
+                           &ms);
             if (e != hipSuccess) { st = hip_fail(e, "autotune"); break; }
             if (ms < best) {
                 best = ms;
@@ -659,14 +770,42 @@ lbm_status batch_tune(lbm_ctx* c, const char* path) {
         }
         if (st != LBM_OK) break;
     }
+    if (st == LBM_OK && spl != 1) {
+        for (int tr : tb_rows) {
+            for (int tw : tb_waves) {
+                hipError_t e = batch_tb_tables(c, tr, tw);
+                if (e != hipSuccess) { st = hip_fail(e, "two-step tables"); break; }
+                c->b_tb_rows = tr;
+                c->b_tb_waves = tw;
+                float ms = 0;
+                e = time_steps(c, e0, e1, 2,
+                               [&](int from) { return batch_step2(c, from, c->stream); }, &ms);
+                if (e != hipSuccess) { st = hip_fail(e, "autotune"); break; }
+                if (ms < best_tb) {
+                    best_tb = ms;
+                    btr = tr;
+                    btw = tw;
+                }
+            }
+            if (st != LBM_OK) break;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    c->b_tb_rows = 0;
     if (st != LBM_OK) return st;
     c->b_wg = br;
     c->b_npt = bn;
     HIP_TRY(batch_tables(c, 64 * bn, br), "tile tables");
     c->b_nwg = bg > 0 ? bg : c->b_ntiles;
-    cache_store(path, key, br, bn, bg);
+    const int use_tr = (btr > 0 && (spl == 2 || best_tb < best)) ? btr : 0;
+    c->b_tb_nwg = 0;
+    if (use_tr > 0) {
+        HIP_TRY(batch_tb_tables(c, use_tr, btw), "two-step tables");
+        c->b_tb_rows = use_tr;
+        c->b_tb_waves = btw;
+    }
+    cache_store(path, key, br, bn, bg, use_tr, btw);
     return LBM_OK;
 }
 
@@ -1051,6 +1190,9 @@ lbm_status lbm_batch_init(lbm_ctx** out, int32_t n, const lbm_params* p,
     c->b_off_tiles = L.off_tiles;
     c->b_off_part = L.off_part;
     c->b_max_tiles = L.max_tiles;
+    c->b_off_cav2 = L.off_cav2;
+    c->b_off_tbwg = L.off_tbwg;
+    c->b_max_tbwg = L.max_tbwg;
     c->bp.assign(p, p + n);
     c->boff = L.off;
     for (int i = 0; i < n; ++i) {
@@ -1099,6 +1241,13 @@ lbm_status lbm_batch_step(lbm_ctx* c, int64_t nsteps) {
             HIP_TRY(hipGraphLaunch(c->gexec[c->cur], c->stream), "graph launch");
             left -= kBatchGraphSteps;
             c->step += kBatchGraphSteps;
+        }
+    }
+    if (c->b_tb_rows > 0) {
+        for (; left >= 2; left -= 2) {
+            HIP_TRY(batch_step2(c, c->cur, c->stream), "batch step launch");
+            c->cur = 1 - c->cur;
+            c->step += 2;
         }
     }
     for (; left > 0; --left) {
@@ -1201,6 +1350,10 @@ lbm_status lbm_batch_shape(const lbm_ctx* c, int32_t* out) {
     out[1] = 64 * c->b_wg;
     out[2] = c->b_nwg;
     out[3] = kBatchGraphSteps;
+    out[4] = c->b_tb_rows > 0 ? 2 : 1;
+    out[5] = c->b_tb_rows;
+    out[6] = c->b_tb_nwg;
+    out[7] = c->b_tb_rows > 0 ? c->b_tb_waves : 0;
     return LBM_OK;
 }
 

@@ -8,6 +8,7 @@
 // result is bitwise that of its own plain run.
 #include "lbm_device.hpp"
 #include "lbm_internal.hpp"
+#include "lbm_tb2.hpp"
 
 namespace lbm {
 
@@ -98,6 +99,47 @@ hipError_t launch_batch_step(const void* src, void* dst, const BatchTable<R>& T,
     }
 }
 
+// Two steps per launch for every cavity (the single-cavity two-step kernel's work, uniform
+// medium per cavity), TW strips (wavefronts) per work-group: narrow cavities leave fewer
+// wavefronts idle with fewer strips per group.  The logical work-groups of all cavities form
+// one list: wg_cav[w] is the cavity of logical work-group w, and for that cavity C.tile0 is its
+// first logical work-group and C.tiles_x its number of strip groups.
+template <typename S, typename R, int TW>
+__global__ __launch_bounds__(64 * TW) void batch_tb2_kernel(
+    const S* __restrict__ src, S* __restrict__ dst, const BatchCavity* __restrict__ cav,
+    const Phys<R>* __restrict__ phys, const int* __restrict__ wg_cav, int rows) {
+    const int wg = tb_logical_group();
+    const int c = wg_cav[wg];
+    const BatchCavity C = cav[c];
+    const Phys<R> P = phys[c];
+    const int lw = wg - C.tile0;
+    const int nstrips = (C.G.nx + kTbCols - 1) / kTbCols;
+    const int strip = (lw % C.tiles_x) * TW + (threadIdx.x >> 6), seg = lw / C.tiles_x;
+    tb2_segment<S, R, false>(src + C.off, dst + C.off, (const S*)nullptr, C.G, P, strip,
+                             strip < nstrips, seg, rows);
+}
+
+template <typename S, typename R>
+hipError_t launch_batch_tb2(const void* src, void* dst, const BatchTable<R>& T, int rows,
+                            int waves, hipStream_t s) {
+    switch (waves) {
+        case 1:
+            batch_tb2_kernel<S, R, 1><<<T.ntiles, 64, 0, s>>>((const S*)src, (S*)dst, T.cav,
+                                                              T.phys, T.tile_cav, rows);
+            break;
+        case 2:
+            batch_tb2_kernel<S, R, 2><<<T.ntiles, 128, 0, s>>>((const S*)src, (S*)dst, T.cav,
+                                                               T.phys, T.tile_cav, rows);
+            break;
+        case 4:
+            batch_tb2_kernel<S, R, 4><<<T.ntiles, 256, 0, s>>>((const S*)src, (S*)dst, T.cav,
+                                                               T.phys, T.tile_cav, rows);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template hipError_t launch_batch_step<float, float>(const void*, void*, const BatchTable<float>&,
                                                     int, int, int, hipStream_t);
 template hipError_t launch_batch_step<double, double>(const void*, void*,
@@ -106,5 +148,13 @@ template hipError_t launch_batch_step<double, double>(const void*, void*,
 template hipError_t launch_batch_step<float, double>(const void*, void*,
                                                      const BatchTable<double>&, int, int, int,
                                                      hipStream_t);
+template hipError_t launch_batch_tb2<float, float>(const void*, void*, const BatchTable<float>&,
+                                                   int, int, hipStream_t);
+template hipError_t launch_batch_tb2<double, double>(const void*, void*,
+                                                     const BatchTable<double>&, int, int,
+                                                     hipStream_t);
+template hipError_t launch_batch_tb2<float, double>(const void*, void*,
+                                                    const BatchTable<double>&, int, int,
+                                                    hipStream_t);
 
 }  // namespace lbm

@@ -10,6 +10,12 @@ namespace lbm {
 constexpr int kTileX = 256;      // nodes (work-items) per work-group of the step kernel
 constexpr int kObserveWG = 512;  // work-groups of the observables pass
 constexpr int kPitchAlign = 64;  // row pitch in elements
+// Two steps per launch: columns a wavefront's strip writes, strips per work-group, the number
+// of resident-set rounds the segment height aims for, and the shortest segment.
+constexpr int kTbCols = 62;
+constexpr int kTbWaves = 4;
+constexpr int kTbRounds = 6;
+constexpr int kTbMinRows = 8;
 
 // Launchers take S, the storage type of populations and medium planes, and R, the arithmetic
 // type; instantiated for (float, float), (double, double) and (float, double).
@@ -77,6 +83,13 @@ struct BatchTable {
     int ncav;
     int ntiles;
 };
+
+// Two steps per launch for every cavity of a batch: T.tile_cav maps each logical work-group to
+// its cavity, whose tile0 is its first work-group and tiles_x its number of strip groups (of
+// `waves` strips: 1, 2 or 4); rows: rows per segment.
+template <typename S, typename R>
+hipError_t launch_batch_tb2(const void* src, void* dst, const BatchTable<R>& T, int rows,
+                            int waves, hipStream_t s);
 
 // rows: rows per tile (work-group = 64 * rows work-items); nodes_x: 64-node segments per
 // work-item along x; nwg >= ntiles: one tile per work-group, else chunked persistent.

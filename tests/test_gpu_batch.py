@@ -34,22 +34,27 @@ def small_batch(dtype):
     return params, phis
 
 
+@pytest.mark.parametrize("spl", [1, 2])
 @pytest.mark.parametrize("dtype", ["fp32", "fp64", "fp32_f64"])
-def test_batch_equals_standalone_runs_bitwise(dtype, tmp_path):
+def test_batch_equals_standalone_runs_bitwise(dtype, spl, tmp_path):
+    """One step per launch and two (the batched two-step kernel, forced through the first
+    cavity's steps_per_launch), through graph replays and an odd remainder."""
     params, phis = small_batch(dtype)
+    params[0] = dict(params[0], steps_per_launch=spl)
     b = Batch(params, phis, tune_cache_path=str(tmp_path / "tune.txt"))
-    b.step(150)           # graph replays + remainder
+    assert b.shape()[4] == spl
+    b.step(151)           # graph replays + remainder (odd: ends with one single step)
     s, obs = b.observables()
     assert s == 0
     for i, (p, phi) in enumerate(zip(params, phis)):
         c = Cavity(p, phi_uniform=phi)
-        c.step(150)
+        c.step(151)
         ref_obs = c.observables()
         got = b.fields(i)
         for k in FIELDS:
             assert torch.equal(got[k], ref_obs[k]), (i, k)
         assert obs[i]["nu_hot"] == ref_obs["nu_hot"]
-        assert obs[i]["step"] == 150
+        assert obs[i]["step"] == 151
         c.close()
     b.close()
 
@@ -89,7 +94,14 @@ def test_autotuner_caches_its_choice(tmp_path):
     a = Batch(params, phis, tune_cache_path=path)
     shape = a.shape()
     lines = open(path).read().splitlines()
-    assert len(lines) == 1 and lines[0].split()[0].startswith(("gfx", "unknown"))
+    # key: format version | device architecture | dtype | hash of the shapes | steps setting;
+    # then rows per tile, segments per work-item, work-groups, two-step rows per segment and
+    # strips per work-group
+    assert len(lines) == 1 and len(lines[0].split()) == 6
+    key = lines[0].split()[0].split("|")
+    assert key[0] == "v3" and key[1].startswith(("gfx", "unknown")) and key[2] == "fp32"
+    assert key[4] == "s0" and int(lines[0].split()[4]) in (0, 8, 12, 16, 24)
+    assert int(lines[0].split()[5]) in (1, 2, 4)
     b = Batch(params, phis, tune_cache_path=path)       # served from the cache
     assert b.shape() == shape
     assert len(open(path).read().splitlines()) == 1
@@ -98,6 +110,7 @@ def test_autotuner_caches_its_choice(tmp_path):
     assert len(open(path).read().splitlines()) == 2
     wg, npt = shape[1], shape[0]
     assert wg in (64, 128, 256, 512) and npt in (1, 2, 4) and shape[3] % 2 == 0
+    assert shape[4] in (1, 2) and (shape[5] > 0) == (shape[4] == 2)
 
 
 def test_batch_rejects_mixed_dtypes_and_tapes():
