@@ -112,11 +112,35 @@ def cpu_baseline(w, budget_s=15.0):
     lat.step(steps)
     dt = time.perf_counter() - t0
     n = w["params"]["nx"] * w["params"]["ny"]
+    # the same oracle on one thread, over a shorter sample
+    ref.set_threads(1)
+    t0 = time.perf_counter()
+    lat.step(1)
+    t1 = time.perf_counter() - t0
+    steps1 = max(1, min(50, int(budget_s / 3 / max(t1, 1e-6))))
+    t0 = time.perf_counter()
+    lat.step(steps1)
+    dt1 = time.perf_counter() - t0
+    ref.set_threads(cores)
     lat.close()
     return {"value": round(n * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": cores,
             "kind": "oracle",
             "sample": f"{steps} FP64 steps of the full {w['params']['nx']}^2 workload "
-                      f"(after 1 untimed step), {dt:.1f} s"}
+                      f"(after 1 untimed step), {dt:.1f} s",
+            "cpu_model": cpu_model(),
+            "one_thread": {"value": round(n * steps1 / dt1 / 1e6, 3), "unit": "MLUPS",
+                           "sample": f"{steps1} further FP64 steps on one thread, {dt1:.1f} s"}}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def leg_batched(torch, steps=1000):
