@@ -114,6 +114,9 @@ lbm_status validate(const lbm_params& p) {
         return fail(LBM_E_INVAL, "layout %d is not LBM_LAYOUT_PULL or LBM_LAYOUT_AA", p.layout);
     if (p.steps_per_launch < 0 || p.steps_per_launch > 2)
         return fail(LBM_E_INVAL, "steps_per_launch = %d is not 0, 1 or 2", p.steps_per_launch);
+    if (p.steps_per_launch == 2 &&
+        pitch * (long long)p.ny * kPlanes * (long long)storage_bytes(p.dtype) >= (1LL << 31))
+        return fail(LBM_E_UNSUPPORTED, "two steps per launch need a state below 2 GiB");
     if (p.layout == LBM_LAYOUT_AA && p.checkpoint_every > 0)
         return fail(LBM_E_UNSUPPORTED, "the AA layout has no adjoint tape");
     const Derived d = derive(p);
@@ -445,6 +448,9 @@ lbm_status batch_layout(int32_t n, const lbm_params* p, BatchLayout* L) {
         if (p[i].layout != LBM_LAYOUT_PULL)
             return fail(LBM_E_UNSUPPORTED, "cavity %d: a batch uses the pull layout", i);
         const Geo G = make_geo(p[i]);
+        if (p[0].steps_per_launch == 2 && !tb2_fits(G, storage_bytes(dt)))
+            return fail(LBM_E_UNSUPPORTED,
+                        "cavity %d: two steps per launch need a state below 2 GiB", i);
         L->off.push_back(elems);
         elems += (long long)kPlanes * G.plane;
         elems = (elems + 63) / 64 * 64;  // 256-byte alignment in FP32
@@ -700,11 +706,11 @@ hipError_t time_steps(lbm_ctx* c, hipEvent_t e0, hipEvent_t e1, int steps_per_la
 
 // Autotuner, on the batch itself.  The one-step kernel: every supported tile shape (rows per
 // work-group x 64-node segments per work-item), with one tile per work-group and with chunked
-// persistent grids of 2..16 work-groups per CU.  The two-step kernel: segments of 8, 12, 16
-// and 24 rows with 1, 2 or 4 strips per work-group.  It keeps the fastest per step (the one-step shape is kept either way, for odd
-// step counts), unless steps_per_launch of the first cavity forces one or two steps per
-// launch.  The result is cached per (device, dtype, cavity shapes, that setting) in
-// tune_cache_path.
+// persistent grids of 2..16 work-groups per CU.  The two-step kernel: segments of 6, 8, 12,
+// 16 and 24 rows with 1, 2 or 4 strips per work-group.  It keeps the fastest per step (the
+// one-step shape is kept either way, for odd step counts), unless steps_per_launch of the
+// first cavity forces one or two steps per launch.  The result is cached per (device, dtype,
+// cavity shapes, that setting) in tune_cache_path.
 lbm_status batch_tune(lbm_ctx* c, const char* path) {
     int cu = 256;
     int dev = 0;
@@ -742,7 +748,7 @@ lbm_status batch_tune(lbm_ctx* c, const char* path) {
     const int shapes[10][2] = {{1, 1}, {1, 2}, {1, 4}, {2, 1}, {2, 2}, {2, 4},
                                {4, 1}, {4, 2}, {4, 4}, {8, 1}};
     const int per_cu[5] = {0, 2, 4, 8, 16};  // 0: one tile per work-group
-    const int tb_rows[4] = {8, 12, 16, 24};
+    const int tb_rows[5] = {6, 8, 12, 16, 24};
     const int tb_waves[3] = {1, 2, 4};
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "event");
@@ -758,8 +764,8 @@ lbm_status batch_tune(lbm_ctx* c, const char* path) {
             c->b_npt = sh[1];
             c->b_nwg = pc == 0 ? c->b_ntiles : std::min(c->b_ntiles, pc * cu);
             float ms = 0;
-            e = time_steps(c, e0, e1, 1, [&](int from) { return batch_step_once(c, from, c->stream); },
-                           &ms);
+            e = time_steps(
+                c, e0, e1, 1, [&](int from) { return batch_step_once(c, from, c->stream); }, &ms);
             if (e != hipSuccess) { st = hip_fail(e, "autotune"); break; }
             if (ms < best) {
                 best = ms;
@@ -770,7 +776,9 @@ lbm_status batch_tune(lbm_ctx* c, const char* path) {
         }
         if (st != LBM_OK) break;
     }
-    if (st == LBM_OK && spl != 1) {
+    bool fit = true;  // the two-step kernel needs each cavity's state below 2 GiB
+    for (int i = 0; i < c->ncav; ++i) fit = fit && tb2_fits(c->bG[i], storage_bytes(c->p.dtype));
+    if (st == LBM_OK && spl != 1 && fit) {
         for (int tr : tb_rows) {
             for (int tw : tb_waves) {
                 hipError_t e = batch_tb_tables(c, tr, tw);

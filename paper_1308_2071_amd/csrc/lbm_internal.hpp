@@ -14,8 +14,14 @@ constexpr int kPitchAlign = 64;  // row pitch in elements
 // of resident-set rounds the segment height aims for, and the shortest segment.
 constexpr int kTbCols = 62;
 constexpr int kTbWaves = 4;
-constexpr int kTbRounds = 6;
-constexpr int kTbMinRows = 8;
+constexpr int kTbRounds = 12;
+constexpr int kTbMinRows = 6;
+
+// The two-step kernels address a state (the 14 planes) through one raw buffer descriptor and
+// drop stores through an offset of 2^31 past it: they need a state below 2^31 bytes.
+inline bool tb2_fits(const Geo& G, size_t elem_bytes) {
+    return (unsigned long long)kPlanes * (unsigned long long)G.plane * elem_bytes < (1ull << 31);
+}
 
 // Launchers take S, the storage type of populations and medium planes, and R, the arithmetic
 // type; instantiated for (float, float), (double, double) and (float, double).

@@ -305,8 +305,10 @@ int tb_resident_groups() {
 
 // Rows per segment of the two-step kernel.  Long segments amortise the two halo rows of the
 // intermediate step; short-lived work-groups let vertically neighbouring segments run close
-// together in time and keep the tail of the launch short.  Measured on the 4096^2 workload:
-// about 6 rounds of the resident set (12 rows) is best, 1 round (69 rows) is 10 % slower.
+// together in time, keep the tail of the launch short, and start with three rows of loads in
+// flight at once.  Measured on the 4096^2 workload (FP32, MLUPS): 4 rows 63.4k, 5 rows 64.5k,
+// 6 rows (12 rounds of the resident set) 65.1k, 8 rows 64.6k, 12 rows 63.5k; one round (69
+// rows) was 10 % slower than 12 rows.
 int tb_rows(const Geo& G, int nstrips, int resident) {
     const int ngrp = (nstrips + kTbWaves - 1) / kTbWaves;
     const int nseg = resident > 0 ? max(1, kTbRounds * resident / ngrp) : 1;
@@ -330,10 +332,11 @@ void prepare_tb2() {
 // FP64 arithmetic on FP32 storage the kernel holds 190 registers and runs at 2 waves per SIMD,
 // 20 % slower than single steps) and with work-groups for at least a quarter of the resident
 // set at 16-row segments (measured: 1024^2 gains 4 % in FP32 and 23 % in FP64, 4096^2 31 % and
-// 35 %; on 256^2 the few long row loops are latency-bound and run 4x slower fused).
+// 35 %; on 256^2 the few long row loops are latency-bound and run 4x slower fused), and with
+// a state below 2 GiB, which one buffer descriptor addresses.
 template <typename S, typename R>
 bool tb2_pays(const Geo& G, bool per_node_medium) {
-    if (!std::is_same<S, R>::value) return false;
+    if (!std::is_same<S, R>::value || !tb2_fits(G, sizeof(S))) return false;
     const int resident = tb_resident<S, R>(per_node_medium);
     const int nstrips = (G.nx + kTbCols - 1) / kTbCols;
     const long long groups =
@@ -351,6 +354,7 @@ void tb2_shape(const Geo& G, bool per_node_medium, int* rows, int* nwg) {
 template <typename S, typename R>
 hipError_t launch_tb2_step(const void* src, void* dst, const void* med, const Geo& G,
                            const Phys<R>& P, hipStream_t s) {
+    if (!tb2_fits(G, sizeof(S))) return hipErrorInvalidValue;
     const int nstrips = (G.nx + kTbCols - 1) / kTbCols;
     int rows = 0, nwg = 0;
     tb2_shape<S, R>(G, med != nullptr, &rows, &nwg);

@@ -17,6 +17,53 @@ namespace lbm {
 // neighbour's lane, which holds the populations its reconstruction needs.  Per two steps each
 // node's populations cross HBM about once each way (plus the halo of the intermediate step),
 // against twice for two single steps.
+//
+// The state is addressed through raw buffer descriptors: a lane's column offsets are fixed for
+// the whole segment, and a row's plane and row offsets are wave-uniform scalars, so no vector
+// instruction computes an address on the fast path and a few scalar registers replace the 64-bit
+// base of every plane.  A descriptor covers the 14 planes of one state, which must hold fewer
+// than 2^31 bytes (tb2_fits), so that an offset of 2^31 is out of range on its own.
+
+// Fourth descriptor word of a raw buffer on the gfx9 family: 32-bit data format (a zero format
+// makes raw loads return zero), no stride, no swizzle.
+constexpr int kBufWord3 = 0x00020000;
+
+// A per-lane offset at which a buffer access is out of range whatever the scalar offset: the
+// hardware drops such a store and returns zero for such a load.  It needs ranges below 2^31
+// bytes and scalar offsets below 2^31, so that the sum cannot wrap.
+constexpr unsigned kBufOutOfRange = 0x80000000u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, int(bytes), kBufWord3);
+}
+
+// Element at byte offset voff (per lane) + soff (wave-uniform) of a buffer.
+template <typename S>
+__device__ __forceinline__ S buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    if constexpr (sizeof(S) == 4)
+        return __builtin_bit_cast(
+            S, __builtin_amdgcn_raw_buffer_load_b32(r, int(voff), int(soff), 0));
+    else
+        return __builtin_bit_cast(
+            S, __builtin_amdgcn_raw_buffer_load_b64(r, int(voff), int(soff), 0));
+}
+
+template <typename S>
+__device__ __forceinline__ void buf_store(S v, __amdgpu_buffer_rsrc_t r, unsigned voff,
+                                          unsigned soff) {
+    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+    if constexpr (sizeof(S) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, int(voff),
+                                              int(soff), 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, int(voff),
+                                              int(soff), 0);
+}
+
+// A value every lane of the wavefront holds, kept in a scalar register.
+__device__ __forceinline__ unsigned wave_uniform(unsigned v) {
+    return unsigned(__builtin_amdgcn_readfirstlane(int(v)));
+}
 
 // Raw inputs of the intermediate step at one node, loaded one row ahead of their use so that
 // the loads are in flight while the previous row computes: the populations pulled at the node
@@ -28,49 +75,59 @@ struct TbRaw {
     S phi, K;       // medium at the node
 };
 
+// Byte offsets of one lane's columns, fixed over a segment: the node's, and those of the node
+// it pulls from (its inward neighbour on a west or east wall) and of that node's west and east
+// neighbours (wrapping, which only a periodic axis uses).
+struct TbCols {
+    unsigned x, f, fw, fe;
+};
+
+// Loads the raw inputs of the intermediate step at (x, r) for the lane's column.  r is a row
+// of the grid; a row beyond a walled side is never consumed, and its caller passes any valid
+// row instead.  Every load is unconditional, so every field is defined on every path.
 template <typename S, bool PN>
-__device__ __forceinline__ void tb_load(const S* __restrict__ src, const S* __restrict__ med,
-                                        const Geo& G, int x, bool ok, int r, TbRaw<S>& raw) {
-    // every field is assigned on every path (a field set on one branch only would keep the
-    // struct in scratch memory)
-    S phi_f = S(1), K_f = S(1), phi = S(1), K = S(1);
-    if (ok) {
-        const bool onW = G.wallW && x == 0, onE = G.wallE && x == G.nx - 1;
-        const bool onS = G.wallS && r == 0, onN = G.wallN && r == G.ny - 1;
-        const int xf = x + (onW ? 1 : 0) - (onE ? 1 : 0);
-        const int yf = r + (onS ? 1 : 0) - (onN ? 1 : 0);
-        pull<S, S>(src, G, xf, yf, raw.f, raw.g);
-        if constexpr (PN) {
-            constexpr unsigned B = sizeof(S);
-            const unsigned of = (unsigned(yf) * unsigned(G.pitch) + unsigned(xf)) * B;
-            const unsigned o = (unsigned(r) * unsigned(G.pitch) + unsigned(x)) * B;
-            phi_f = at(med, of);
-            K_f = at(plane(med, 1, G.plane), of);
-            phi = at(med, o);
-            K = at(plane(med, 1, G.plane), o);
-        }
+__device__ __forceinline__ void tb_load(__amdgpu_buffer_rsrc_t rs, __amdgpu_buffer_rsrc_t rm,
+                                        const Geo& G, unsigned PB, unsigned RB,
+                                        const TbCols& c, int r, TbRaw<S>& raw) {
+    const bool onS = G.wallS && r == 0, onN = G.wallN && r == G.ny - 1;
+    const int yf = r + (onS ? 1 : 0) - (onN ? 1 : 0);
+    const int ym = yf == 0 ? G.ny - 1 : yf - 1, yp = yf == G.ny - 1 ? 0 : yf + 1;
+    const unsigned s0 = wave_uniform(unsigned(yf) * RB);
+    const unsigned sm = wave_uniform(unsigned(ym) * RB);
+    const unsigned sp = wave_uniform(unsigned(yp) * RB);
+    // the medium first: the loop copies it between registers, and an early load is the one
+    // most likely to have arrived by then
+    if constexpr (PN) {
+        const unsigned sr = wave_uniform(unsigned(r) * RB);
+        raw.phi_f = buf_load<S>(rm, c.f, s0);
+        raw.K_f = buf_load<S>(rm, c.f, s0 + PB);
+        raw.phi = buf_load<S>(rm, c.x, sr);
+        raw.K = buf_load<S>(rm, c.x, sr + PB);
     } else {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) raw.f[i] = S(0);
-#pragma unroll
-        for (int i = 0; i < 5; ++i) raw.g[i] = S(0);
+        raw.phi_f = raw.K_f = raw.phi = raw.K = S(1);
     }
-    raw.phi_f = phi_f;
-    raw.K_f = K_f;
-    raw.phi = phi;
-    raw.K = K;
+    // f_i arrives from (xf - ex_i, yf - ey_i)
+    raw.f[0] = buf_load<S>(rs, c.f, s0);
+    raw.f[1] = buf_load<S>(rs, c.fw, s0 + PB);
+    raw.f[2] = buf_load<S>(rs, c.f, sm + 2 * PB);
+    raw.f[3] = buf_load<S>(rs, c.fe, s0 + 3 * PB);
+    raw.f[4] = buf_load<S>(rs, c.f, sp + 4 * PB);
+    raw.f[5] = buf_load<S>(rs, c.fw, sm + 5 * PB);
+    raw.f[6] = buf_load<S>(rs, c.fe, sm + 6 * PB);
+    raw.f[7] = buf_load<S>(rs, c.fe, sp + 7 * PB);
+    raw.f[8] = buf_load<S>(rs, c.fw, sp + 8 * PB);
+    raw.g[0] = buf_load<S>(rs, c.f, s0 + 9 * PB);
+    raw.g[1] = buf_load<S>(rs, c.fw, s0 + 10 * PB);
+    raw.g[2] = buf_load<S>(rs, c.f, sm + 11 * PB);
+    raw.g[3] = buf_load<S>(rs, c.fe, s0 + 12 * PB);
+    raw.g[4] = buf_load<S>(rs, c.f, sp + 13 * PB);
 }
 
 // The intermediate step at (x, r) from its raw inputs: node_state's arithmetic, then collide,
-// rounded to the storage type.
+// rounded to the storage type; md receives the medium coefficients at (x, r).
 template <typename S, typename R, bool PN>
 __device__ __forceinline__ void tb_finish(const TbRaw<S>& raw, const Geo& G, const Phys<R>& P,
-                                          int x, bool ok, int r, S out[14]) {
-    if (!ok) {
-#pragma unroll
-        for (int i = 0; i < 14; ++i) out[i] = S(0);
-        return;
-    }
+                                          int x, int r, S out[14], Med<R>& md) {
     R f[9], g[5];
 #pragma unroll
     for (int i = 0; i < 9; ++i) f[i] = R(raw.f[i]);
@@ -78,7 +135,6 @@ __device__ __forceinline__ void tb_finish(const TbRaw<S>& raw, const Geo& G, con
     for (int i = 0; i < 5; ++i) g[i] = R(raw.g[i]);
     const bool onW = G.wallW && x == 0, onE = G.wallE && x == G.nx - 1;
     const bool onS = G.wallS && r == 0, onN = G.wallN && r == G.ny - 1;
-    Med<R> md;
     Mac<R> m;
     if constexpr (PN)
         md = medium_from<R>(R(raw.phi), R(raw.K), P);
@@ -99,67 +155,76 @@ __device__ __forceinline__ void tb_finish(const TbRaw<S>& raw, const Geo& G, con
     for (int i = 0; i < 5; ++i) out[9 + i] = S(g[i]);
 }
 
-// Row r of the intermediate step as seen from this lane: wrapped on a periodic axis, absent
-// beyond a walled side.
-__device__ __forceinline__ bool tb_rowc(const Geo& G, bool col_ok, int& r) {
-    if (r >= 0 && r < G.ny) return col_ok;
-    if (G.wallS) return false;
-    r = r < 0 ? r + G.ny : r - G.ny;
-    return col_ok;
+// Row r of the intermediate step: wrapped on a periodic axis; beyond a walled side the row is
+// absent (nothing consumes it) and row 0 stands in for it.
+__device__ __forceinline__ int tb_row(const Geo& G, int r) {
+    if (r >= 0 && r < G.ny) return r;
+    if (G.wallS) return 0;
+    return r < 0 ? r + G.ny : r - G.ny;
 }
 
 // One wavefront's share of a two-step launch: strip `strip` of row segment `seg` (rows per
-// segment `rows`).  Every wavefront of the work-group calls this with the same
-// segment and runs the same rows (an inactive one, past the last strip, loads and stores
-// nothing), since each row ends with a work-group barrier.
+// segment `rows`).  Every wavefront of the work-group calls this with the same segment and
+// runs the same rows (an inactive one, past the last strip, stores nothing), since each row
+// ends with a work-group barrier.
 template <typename S, typename R, bool PN>
 __device__ __forceinline__ void tb2_segment(const S* __restrict__ src, S* __restrict__ dst,
                                             const S* __restrict__ med, const Geo& G,
                                             const Phys<R>& P, int strip, bool active, int seg,
                                             int rows) {
+    constexpr unsigned B = sizeof(S);
+    const unsigned PB = unsigned(G.plane) * B;   // bytes per plane
+    const unsigned RB = unsigned(G.pitch) * B;   // bytes per row
+    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(src, 14 * PB);
+    const __amdgpu_buffer_rsrc_t rd = buf_rsrc(dst, 14 * PB);
+    const __amdgpu_buffer_rsrc_t rm = buf_rsrc(med, PN ? 2 * PB : 0);
     const int lane = threadIdx.x & 63;
     const int x0 = strip * kTbCols;
-    // this lane's column; outside a walled side it computes nothing
+    // this lane's column, wrapped on a periodic axis; outside a walled side (or in an idle
+    // wavefront) it is a stand-in whose results nothing consumes
     int x = x0 - 1 + lane;
-    bool col_ok = active;
     if (x < 0 || x >= G.nx) {
-        col_ok = active && !G.wallW;
         x = x < 0 ? x + G.nx : x - G.nx;
-        if (x < 0 || x >= G.nx) x = 0;  // only reached by an idle wavefront
+        if (x < 0 || x >= G.nx) x = 0;
+    }
+    TbCols cols;
+    {
+        const bool onW = G.wallW && x == 0, onE = G.wallE && x == G.nx - 1;
+        const int xf = x + (onW ? 1 : 0) - (onE ? 1 : 0);
+        cols.x = unsigned(x) * B;
+        cols.f = unsigned(xf) * B;
+        cols.fw = unsigned(xf == 0 ? G.nx - 1 : xf - 1) * B;
+        cols.fe = unsigned(xf == G.nx - 1 ? 0 : xf + 1) * B;
     }
     // lanes 1..kTbCols write step n+2 at their column
     const bool out_lane = active && lane >= 1 && lane <= kTbCols && x0 - 1 + lane < G.nx;
     const int y0 = seg * rows;
     const int y1 = min(y0 + rows, G.ny);
     S a[14], b[14], c[14];  // step n+1 at rows y-1, y, y+1 of this lane's column
-    S phib = S(1), Kb = S(1), phic = S(1), Kc = S(1);  // medium at (x, y) and (x, y + 1)
+    Med<R> mdb, mdc;        // medium at (x, y) and (x, y + 1)
     TbRaw<S> raw;
     {
-        int r = y0 - 1;
-        bool ok = tb_rowc(G, col_ok, r);
-        tb_load<S, PN>(src, med, G, x, ok, r, raw);
-        tb_finish<S, R, PN>(raw, G, P, x, ok, r, a);
-        r = y0;
-        ok = tb_rowc(G, col_ok, r);
-        tb_load<S, PN>(src, med, G, x, ok, r, raw);
-        tb_finish<S, R, PN>(raw, G, P, x, ok, r, b);
-        phib = raw.phi;
-        Kb = raw.K;
-        r = y0 + 1;
-        ok = tb_rowc(G, col_ok, r);
-        tb_load<S, PN>(src, med, G, x, ok, r, raw);
+        Med<R> unused;
+        int r = tb_row(G, y0 - 1);
+        tb_load<S, PN>(rs, rm, G, PB, RB, cols, r, raw);
+        tb_finish<S, R, PN>(raw, G, P, x, r, a, unused);
+        r = tb_row(G, y0);
+        tb_load<S, PN>(rs, rm, G, PB, RB, cols, r, raw);
+        tb_finish<S, R, PN>(raw, G, P, x, r, b, mdb);
+        tb_load<S, PN>(rs, rm, G, PB, RB, cols, tb_row(G, y0 + 1), raw);
+        // 14 stores that the hardware drops, so that on entering the row loop, as on every
+        // later row, the loads in flight are followed by 14 stores: the compiler's wait for
+        // those loads at the top of the loop then leaves the previous row's stores in flight
+        __builtin_amdgcn_sched_barrier(0);  // keep them after the loads
+#pragma unroll
+        for (int i = 0; i < 14; ++i) buf_store<S>(S(0), rd, kBufOutOfRange, i * PB);
     }
-    for (int y = y0; y < y1; ++y) {
-        {
-            int r = y + 1;
-            const bool ok = tb_rowc(G, col_ok, r);
-            tb_finish<S, R, PN>(raw, G, P, x, ok, r, c);
-            phic = raw.phi;
-            Kc = raw.K;
-            r = y + 2;  // issue the next row's loads now; they complete during this row's work
-            const bool ok2 = tb_rowc(G, col_ok, r);
-            tb_load<S, PN>(src, med, G, x, ok2, r, raw);
-        }
+    // y0 < y1 on every segment; the work-group's waves run the same rows
+    int y = y0;
+    do {
+        tb_finish<S, R, PN>(raw, G, P, x, tb_row(G, y + 1), c, mdc);
+        // issue the next row's loads now; they complete during this row's work
+        tb_load<S, PN>(rs, rm, G, PB, RB, cols, tb_row(G, y + 2), raw);
         // gather step n+1 populations arriving at (x, y): f_i from (x - ex_i, y - ey_i)
         const S f1 = __shfl_up(b[1], 1, 64), g1 = __shfl_up(b[10], 1, 64);
         const S f5 = __shfl_up(a[5], 1, 64), f8 = __shfl_up(c[8], 1, 64);
@@ -167,42 +232,45 @@ __device__ __forceinline__ void tb2_segment(const S* __restrict__ src, S* __rest
         const S f6 = __shfl_down(a[6], 1, 64), f7 = __shfl_down(c[7], 1, 64);
         const bool wall = (G.wallW && x == 0) || (G.wallE && x == G.nx - 1) ||
                           (G.wallS && y == 0) || (G.wallN && y == G.ny - 1);
-        if (out_lane && !wall) {
-            R f[9] = {R(b[0]), R(f1), R(a[2]), R(f3), R(c[4]), R(f5), R(f6), R(f7), R(f8)};
-            R g[5] = {R(b[9]), R(g1), R(a[11]), R(g3), R(c[13])};
-            Med<R> md;
-            if constexpr (PN)
-                md = medium_from<R>(R(phib), R(Kb), P);
-            else
-                md = Med<R>{P.phi, P.inv_phi, P.c_lin, P.c_nl};
-            const Mac<R> m = fluid_macros<R>(f, g, md, P);
+        // Step n+2 runs on every lane; lanes that own no output (the strip's two halo lanes,
+        // columns past the grid, wall nodes, which their inward neighbours step) store
+        // through an offset outside the descriptor's range, which the hardware drops.  No
+        // branch guards the stores, so the compiler knows they are issued after this row's
+        // loads on every path and waits only for the loads at the next row (a guarded store
+        // block made it wait for the stores as well, once per row).
+        const bool own = out_lane && !wall;
+        R f[9] = {R(b[0]), R(f1), R(a[2]), R(f3), R(c[4]), R(f5), R(f6), R(f7), R(f8)};
+        R g[5] = {R(b[9]), R(g1), R(a[11]), R(g3), R(c[13])};
+        const Med<R> md = mdb;
+        const Mac<R> m = fluid_macros<R>(f, g, md, P);
+        if (own)
             step_wall_neighbours<R, PN, S>(
                 med, G, P, x, y, f, g, m, md, [&](int xb, int yb, const R* fb, const R* gb) {
-                    const unsigned ob = unsigned(yb) * unsigned(G.pitch) + unsigned(xb);
+                    const unsigned ob =
+                        (unsigned(yb) * unsigned(G.pitch) + unsigned(xb)) * B;
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) plane(dst, i, G.plane)[ob] = S(fb[i]);
+                    for (int i = 0; i < 9; ++i) buf_store<S>(S(fb[i]), rd, ob, i * PB);
 #pragma unroll
-                    for (int i = 0; i < 5; ++i) plane(dst, 9 + i, G.plane)[ob] = S(gb[i]);
+                    for (int i = 0; i < 5; ++i)
+                        buf_store<S>(S(gb[i]), rd, ob, (9 + i) * PB);
                 });
-            collide<R>(f, g, m, md, P);
-            const unsigned o =
-                (unsigned(y) * unsigned(G.pitch) + unsigned(x)) * unsigned(sizeof(S));
-            // plain stores: a strip's edge lines are shared with its neighbour, and merge in
-            // L2 before they go to HBM (non-temporal stores cost 10 % here)
+        collide<R>(f, g, m, md, P);
+        // plain stores: a strip's edge lines are shared with its neighbour, and merge in L2
+        // before they go to HBM (non-temporal stores cost 10 % here)
+        const unsigned vo = own ? cols.x : kBufOutOfRange;
+        const unsigned sy = wave_uniform(unsigned(y) * RB);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) at(plane(dst, i, G.plane), o) = S(f[i]);
+        for (int i = 0; i < 9; ++i) buf_store<S>(S(f[i]), rd, vo, sy + i * PB);
 #pragma unroll
-            for (int i = 0; i < 5; ++i) at(plane(dst, 9 + i, G.plane), o) = S(g[i]);
-        }
+        for (int i = 0; i < 5; ++i) buf_store<S>(S(g[i]), rd, vo, sy + (9 + i) * PB);
 #pragma unroll
         for (int i = 0; i < 14; ++i) {
             a[i] = b[i];
             b[i] = c[i];
         }
-        phib = phic;
-        Kb = Kc;
+        mdb = mdc;
         __syncthreads();
-    }
+    } while (++y < y1);
 }
 
 // Work-groups are dealt round-robin over the 8 XCDs; this maps a launch's work-group index to a

@@ -150,3 +150,22 @@ def test_aa_layout_limits(lbm):
     p = (_abi.LbmParams * 1)(lbm.make_params(nx=16, ny=16, layout="aa"))
     n = C.c_size_t()
     assert _abi.library().lbm_batch_workspace_size(1, p, C.byref(n)) == -6
+
+
+def test_two_steps_per_launch_need_a_state_below_2_gib(lbm):
+    """The two-step kernels address a state through one buffer descriptor and drop the stores of
+    lanes that own no node through an offset of 2^31, so the state must stay below 2^31 bytes."""
+    # 14 planes x 3500 rows x pitch 3520 x 8 B = 1.38 GB in FP64; 4400^2 is 2.17 GB
+    assert status_of(lbm, nx=3500, ny=3500, dtype=1, steps_per_launch=2) == 0
+    assert status_of(lbm, nx=4400, ny=4400, dtype=1, steps_per_launch=2) == -6  # UNSUPPORTED
+    assert status_of(lbm, nx=4400, ny=4400, dtype=1, steps_per_launch=0) == 0   # single steps
+    assert status_of(lbm, nx=4096, ny=4096, dtype=1, steps_per_launch=2) == 0   # 1.88 GB
+    assert status_of(lbm, nx=6500, ny=6500, steps_per_launch=2) == -6           # FP32 2.37 GB
+    from paper_1308_2071_amd import _abi
+    big = lbm.make_params(nx=6500, ny=6500, steps_per_launch=0)
+    small = lbm.make_params(nx=64, ny=64, steps_per_launch=2)
+    p = (_abi.LbmParams * 2)(small, big)
+    n = C.c_size_t()
+    assert _abi.library().lbm_batch_workspace_size(2, p, C.byref(n)) == -6
+    p = (_abi.LbmParams * 2)(lbm.make_params(nx=64, ny=64), big)
+    assert _abi.library().lbm_batch_workspace_size(2, p, C.byref(n)) == 0
