@@ -104,6 +104,8 @@ typedef struct {
                              /* faster (large grids, storage type = arithmetic type); 2: fuse */
                              /* wherever the pull layout without a tape allows; 1: one step  */
                              /* per launch.  Results are bitwise the same in every case.      */
+                             /* Fusing needs a state (14 planes) below 2 GiB: 2 beyond it    */
+                             /* gives LBM_E_UNSUPPORTED, 0 steps one at a time.               */
 } lbm_params;
 
 /* Observables at the current time level. */
@@ -203,8 +205,9 @@ lbm_status lbm_batch_workspace_size(int32_t n, const lbm_params* p, size_t* byte
 /* Create a batch of n cavities.  tune_cache_path: file where the launch shape picked by the
  * autotuner is cached per (device, dtype, cavity set); NULL disables tuning (default shape).
  * The autotuner also times two steps per launch and keeps it where it is faster;
- * p[0].steps_per_launch = 1 or 2 forces one or two (the other cavities' values are ignored).
- * Results are bitwise the same either way. */
+ * p[0].steps_per_launch = 1 or 2 forces one or two (the other cavities' values are ignored;
+ * 2 gives LBM_E_UNSUPPORTED if a cavity's state reaches 2 GiB, where the autotuner keeps one
+ * step per launch).  Results are bitwise the same either way. */
 lbm_status lbm_batch_init(lbm_ctx** out, int32_t n, const lbm_params* p,
                           const double* phi_uniform, void* workspace, size_t ws_bytes,
                           void* hip_stream, const char* tune_cache_path);
