@@ -328,20 +328,24 @@ void prepare_tb2() {
     (void)tb_resident<S, R>(false);
 }
 
-// Whether two steps per launch beat one: only with equal storage and arithmetic types (with
-// FP64 arithmetic on FP32 storage the kernel holds 190 registers and runs at 2 waves per SIMD,
-// 20 % slower than single steps) and with work-groups for at least a quarter of the resident
-// set at 16-row segments (measured: 1024^2 gains 4 % in FP32 and 23 % in FP64, 4096^2 31 % and
-// 35 %; on 256^2 the few long row loops are latency-bound and run 4x slower fused), and with
+// Whether two steps per launch beat one.  Measured (fused / single MLUPS, per-node medium):
+//   FP32           4096^2 1.38, 2048^2 1.26, 1024^2 1.17, 512^2 0.52, 256^2 0.34
+//   FP64           4096^2 1.53, 2048^2 1.31, 1024^2 1.19, 512^2 0.58
+//   FP32 storage,  4096^2 1.04, 2048^2 0.83, 1024^2 0.64 (225 registers, 2 waves per SIMD)
+//   FP64 arithmetic
+// On small grids the few long row loops are latency-bound.  With equal types the kernel fuses
+// when its work-groups at 16-row segments number at least a quarter of the resident set, with
+// FP64 arithmetic on FP32 storage when they number eight times the resident set; and only for
 // a state below 2 GiB, which one buffer descriptor addresses.
 template <typename S, typename R>
 bool tb2_pays(const Geo& G, bool per_node_medium) {
-    if (!std::is_same<S, R>::value || !tb2_fits(G, sizeof(S))) return false;
+    if (!tb2_fits(G, sizeof(S))) return false;
     const int resident = tb_resident<S, R>(per_node_medium);
     const int nstrips = (G.nx + kTbCols - 1) / kTbCols;
     const long long groups =
         (long long)((nstrips + kTbWaves - 1) / kTbWaves) * ((G.ny + 15) / 16);
-    return resident > 0 && 4 * groups >= resident;
+    if (resident <= 0) return false;
+    return std::is_same<S, R>::value ? 4 * groups >= resident : groups >= 8LL * resident;
 }
 
 template <typename S, typename R>
