@@ -180,7 +180,8 @@ lbm_status lbm_step_shape(const lbm_ctx* c, int32_t* out);
  * derivative of the n-step discrete map from rest (phi held fixed for dK, K for dphi).  Both
  * outputs are device FP64 arrays [ny][nx]; either may be NULL.  Needs checkpoint_every > 0
  * (else LBM_E_STATE).  The forward state is left unchanged.  Uses the checkpoints written by
- * lbm_step and recomputes each segment between checkpoints. */
+ * lbm_step and recomputes each segment between checkpoints, the segment before the one being
+ * swept on a second, internal stream that is ordered with the caller's by events. */
 lbm_status lbm_grad(lbm_ctx* c, double dJ, void* dJ_dphi, void* dJ_dK);
 
 /* Size in bytes of a saved state (populations plus the step counter). */

@@ -196,7 +196,8 @@ struct Layout {
     size_t off_part;      // observables partials + results
     size_t off_tape;      // checkpoints
     size_t n_ckpt;
-    size_t off_seg;       // C states of one segment
+    size_t off_seg;       // two banks of C states: the segment the adjoint is sweeping, and
+                          // the one before it, recomputed meanwhile on a second stream
     size_t off_lam[2];
     size_t off_gacc;      // 2 FP64 planes
     size_t total;
@@ -225,7 +226,7 @@ Layout make_layout(const lbm_params& p, int64_t nsteps_max, bool med_planes) {
         L.n_ckpt = std::max<size_t>(1, (size_t(std::max<int64_t>(nsteps_max, 1)) + C - 1) / C);
         o += L.n_ckpt * L.state_bytes;
         L.off_seg = o;
-        o += C * L.state_bytes;
+        o += 2 * C * L.state_bytes;
         L.off_lam[0] = o;
         o += L.state_bytes;
         L.off_lam[1] = o;
@@ -258,6 +259,9 @@ struct lbm_ctx {
     hipStream_t cap = nullptr;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int gsteps = 0;
+    // adjoint: the stream that recomputes the next segment, and its events
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_rec[2] = {nullptr, nullptr}, ev_bwd[2] = {nullptr, nullptr}, ev_go = nullptr;
     // batched form
     int ncav = 0;
     std::vector<lbm_params> bp;
@@ -277,7 +281,9 @@ struct lbm_ctx {
     void* medp() const { return med ? ws + L.off_med : nullptr; }
     double* part() const { return (double*)(ws + L.off_part); }
     void* ckpt(size_t k) const { return ws + L.off_tape + k * L.state_bytes; }
-    void* seg(size_t k) const { return ws + L.off_seg + k * L.state_bytes; }
+    void* seg(int bank, size_t k) const {
+        return ws + L.off_seg + (size_t(bank) * size_t(p.checkpoint_every) + k) * L.state_bytes;
+    }
     void* lam(int i) const { return ws + L.off_lam[i]; }
     double* gacc(int i) const { return (double*)(ws + L.off_gacc) + size_t(i) * G.plane; }
 };
@@ -1107,6 +1113,15 @@ lbm_status lbm_grad(lbm_ctx* c, double dJ, void* dJ_dphi, void* dJ_dK) {
                 "zero adjoint");
     int lc = 0;  // buffer holding the adjoint of the latest state
     if (N > 0) {
+        if (!c->aux) {
+            HIP_TRY(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking), "stream create");
+            for (int b = 0; b < 2; ++b) {
+                HIP_TRY(hipEventCreateWithFlags(&c->ev_rec[b], hipEventDisableTiming), "event");
+                HIP_TRY(hipEventCreateWithFlags(&c->ev_bwd[b], hipEventDisableTiming), "event");
+            }
+            HIP_TRY(hipEventCreateWithFlags(&c->ev_go, hipEventDisableTiming), "event");
+        }
+        hipStream_t aux = c->aux;
         const double LdT = c->d.L / c->d.dT;
         HIP_TRY(with_types(c->p.dtype,
                            [&](auto stt, auto rt) {
@@ -1116,27 +1131,55 @@ lbm_status lbm_grad(lbm_ctx* c, double dJ, void* dJ_dphi, void* dJ_dK) {
                            }),
                 "adjoint seed");
         const int64_t nseg = (N + C - 1) / C;
-        for (int64_t sg = nseg - 1; sg >= 0; --sg) {
-            const int64_t n0 = sg * C, len = std::min<int64_t>(C, N - n0);
-            // recompute X^{n0} .. X^{n0+len-1} from the checkpoint
-            HIP_TRY(hipMemcpyAsync(c->seg(0), c->ckpt(size_t(sg)), c->L.state_bytes,
-                                   hipMemcpyDeviceToDevice, st),
-                    "segment restore");
-            for (int64_t k = 1; k < len; ++k)
-                HIP_TRY(step_once(c, c->seg(size_t(k - 1)), c->seg(size_t(k)), st),
-                        "recompute launch");
-            for (int64_t k = len - 1; k >= 0; --k) {
-                const void* X = c->seg(size_t(k));
-                HIP_TRY(with_types(c->p.dtype,
-                                   [&](auto stt, auto rt) {
-                                       LBM_TYPES(stt, rt)
-                                       return launch_adjoint_step<S, R>(
-                                           X, c->lam(lc), c->lam(1 - lc), c->medp(), gphi, gK,
-                                           c->G, phys<R>(c), st);
-                                   }),
-                        "adjoint step launch");
-                lc = 1 - lc;
+        // X^{n0} .. X^{n0+len-1} of segment sg, recomputed from its checkpoint into bank sg % 2
+        auto recompute = [&](int64_t sg) -> hipError_t {
+            const int bank = int(sg & 1);
+            const int64_t len = std::min<int64_t>(C, N - sg * C);
+            hipError_t e = hipMemcpyAsync(c->seg(bank, 0), c->ckpt(size_t(sg)),
+                                          c->L.state_bytes, hipMemcpyDeviceToDevice, aux);
+            for (int64_t k = 1; k < len && e == hipSuccess; ++k)
+                e = step_once(c, c->seg(bank, size_t(k - 1)), c->seg(bank, size_t(k)), aux);
+            if (e == hipSuccess) e = hipEventRecord(c->ev_rec[bank], aux);
+            return e;
+        };
+        // The backward sweep of segment sg (on the caller's stream) overlaps the recompute of
+        // segment sg - 1 (on aux); a bank is recomputed only after the sweep that last read it.
+        lbm_status st_out = LBM_OK;
+        auto sweep = [&]() -> lbm_status {
+            HIP_TRY(hipEventRecord(c->ev_go, st), "event");
+            HIP_TRY(hipStreamWaitEvent(aux, c->ev_go, 0), "stream wait");
+            HIP_TRY(recompute(nseg - 1), "recompute launch");
+            for (int64_t sg = nseg - 1; sg >= 0; --sg) {
+                const int bank = int(sg & 1);
+                const int64_t len = std::min<int64_t>(C, N - sg * C);
+                if (sg > 0) {
+                    if (sg + 1 < nseg)
+                        HIP_TRY(hipStreamWaitEvent(aux, c->ev_bwd[1 - bank], 0), "stream wait");
+                    HIP_TRY(recompute(sg - 1), "recompute launch");
+                }
+                HIP_TRY(hipStreamWaitEvent(st, c->ev_rec[bank], 0), "stream wait");
+                for (int64_t k = len - 1; k >= 0; --k) {
+                    const void* X = c->seg(bank, size_t(k));
+                    HIP_TRY(with_types(c->p.dtype,
+                                       [&](auto stt, auto rt) {
+                                           LBM_TYPES(stt, rt)
+                                           return launch_adjoint_step<S, R>(
+                                               X, c->lam(lc), c->lam(1 - lc), c->medp(), gphi,
+                                               gK, c->G, phys<R>(c), st);
+                                       }),
+                            "adjoint step launch");
+                    lc = 1 - lc;
+                }
+                HIP_TRY(hipEventRecord(c->ev_bwd[bank], st), "event");
             }
+            return LBM_OK;
+        };
+        st_out = sweep();
+        if (st_out != LBM_OK) {
+            // leave no work in flight on the second stream
+            (void)hipStreamSynchronize(aux);
+            (void)hipStreamSynchronize(st);
+            return st_out;
         }
     }
     if (dJ_dphi)
@@ -1150,9 +1193,16 @@ lbm_status lbm_grad(lbm_ctx* c, double dJ, void* dJ_dphi, void* dJ_dK) {
 lbm_status lbm_destroy(lbm_ctx* c) {
     if (!c) return LBM_OK;
     hipError_t e = c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize();
+    if (c->aux) (void)hipStreamSynchronize(c->aux);
     for (int i = 0; i < 2; ++i)
         if (c->gexec[i]) (void)hipGraphExecDestroy(c->gexec[i]);
     if (c->cap) (void)hipStreamDestroy(c->cap);
+    for (int i = 0; i < 2; ++i) {
+        if (c->ev_rec[i]) (void)hipEventDestroy(c->ev_rec[i]);
+        if (c->ev_bwd[i]) (void)hipEventDestroy(c->ev_bwd[i]);
+    }
+    if (c->ev_go) (void)hipEventDestroy(c->ev_go);
+    if (c->aux) (void)hipStreamDestroy(c->aux);
     delete c;
     if (e != hipSuccess) return hip_fail(e, "lbm_destroy");
     return LBM_OK;

@@ -131,8 +131,8 @@ def test_workspace_grows_with_tape(lbm):
     tape = lbm.lbm_workspace_size(lbm.make_params(nx=64, ny=64, checkpoint_every=100), 2000)
     state = 14 * 64 * 64 * 4
     assert base >= 2 * state
-    # 20 checkpoints + 100 segment states + 2 adjoint buffers
-    assert tape - base >= (20 + 100 + 2) * state
+    # 20 checkpoints + two banks of 100 segment states + 2 adjoint buffers
+    assert tape - base >= (20 + 200 + 2) * state
 
 
 def test_aa_layout_halves_the_state_memory(lbm):
