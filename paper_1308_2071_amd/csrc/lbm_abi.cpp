@@ -1144,7 +1144,6 @@ lbm_status lbm_grad(lbm_ctx* c, double dJ, void* dJ_dphi, void* dJ_dK) {
         };
         // The backward sweep of segment sg (on the caller's stream) overlaps the recompute of
         // segment sg - 1 (on aux); a bank is recomputed only after the sweep that last read it.
-        lbm_status st_out = LBM_OK;
         auto sweep = [&]() -> lbm_status {
             HIP_TRY(hipEventRecord(c->ev_go, st), "event");
             HIP_TRY(hipStreamWaitEvent(aux, c->ev_go, 0), "stream wait");
@@ -1174,7 +1173,7 @@ lbm_status lbm_grad(lbm_ctx* c, double dJ, void* dJ_dphi, void* dJ_dK) {
             }
             return LBM_OK;
         };
-        st_out = sweep();
+        const lbm_status st_out = sweep();
         if (st_out != LBM_OK) {
             // leave no work in flight on the second stream
             (void)hipStreamSynchronize(aux);
