@@ -21,7 +21,7 @@ import pytest
 import torch
 
 from oracle import ref
-from paper_1308_2071_amd import Cavity, workloads
+from paper_1308_2071_amd import Cavity, lbm_step_shape, workloads
 
 pytestmark = pytest.mark.gpu
 
@@ -98,11 +98,12 @@ def oracle_run(n, steps):
     return r
 
 
-def gpu_run(n, steps, dtype):
+def gpu_run(n, steps, dtype, steps_per_launch=0):
     w = workloads.roofline4096()
     phi = torch.from_numpy(w["phi"][:n, :n].astype(np.float32))
     K = torch.from_numpy(w["K"][:n, :n].astype(np.float32))
-    cav = Cavity(dict(w["params"], nx=n, ny=n, dtype=dtype), phi=phi, K=K)
+    cav = Cavity(dict(w["params"], nx=n, ny=n, dtype=dtype, steps_per_launch=steps_per_launch),
+                 phi=phi, K=K)
     cav.step(steps)
     g = cav.observables()
     cav.close()
@@ -114,9 +115,34 @@ def test_roofline4096_first_10_steps_full_field(dtype):
     compare_full(gpu_run(4096, 10, dtype), oracle_run(4096, 10), dtype)
 
 
+@pytest.mark.parametrize("spl", [0, 2])
 @pytest.mark.parametrize("dtype", ["fp32", "fp32_f64"])
-def test_roofline4096_crop512_2000_steps(dtype):
-    compare_full(gpu_run(512, 2000, dtype), oracle_run(512, 2000), dtype, floor=0.0)
+def test_roofline4096_crop512_2000_steps(dtype, spl):
+    """The crop steps one at a time by default (512^2 is too small to fuse); spl = 2 runs the
+    two-step kernel that times the full workload over the same 2000 steps."""
+    compare_full(gpu_run(512, 2000, dtype, spl), oracle_run(512, 2000), dtype, floor=0.0)
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp32_f64"])
+def test_roofline4096_fused_equals_single_steps_over_1000_steps(dtype):
+    """The benchmark's launch configuration on the full field, beyond what the oracle reaches
+    there: the default time loop (two steps per launch on this grid) equals one step per launch
+    bitwise after 1000 steps, and after an odd count (a single step ends the run)."""
+    w = workloads.roofline4096()
+    phi = torch.from_numpy(w["phi"].astype(np.float32))
+    K = torch.from_numpy(w["K"].astype(np.float32))
+    fused = Cavity(dict(w["params"], dtype=dtype), phi=phi, K=K)
+    single = Cavity(dict(w["params"], dtype=dtype, steps_per_launch=1), phi=phi, K=K)
+    assert lbm_step_shape(fused.ctx)[0] == 2 and lbm_step_shape(single.ctx)[0] == 1
+    for n in (1000, 1):
+        fused.step(n)
+        single.step(n)
+        a, b = fused.observables(), single.observables()
+        for k in FIELDS:
+            assert torch.equal(a[k], b[k]), (n, k)
+        assert a["nu_hot"] == b["nu_hot"] and a["step"] == b["step"]
+    fused.close()
+    single.close()
 
 
 # adjoint: gradient field vs the oracle adjoint (of max |grad|), J, and probes vs the Richardson
