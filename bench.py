@@ -143,9 +143,10 @@ def cpu_model():
     return "unknown"
 
 
-def leg_batched(torch, steps=1000):
-    """64 uneven cavities in one launch per step (graph-replayed, autotuned), against the same
-    cavities stepped by the plain path: 64 launches per step, and each cavity's own graph."""
+def leg_batched(torch, steps=10000):
+    """64 uneven cavities, 10k steps each, in one launch per step or per two steps
+    (graph-replayed, autotuned), against the same cavities stepped by the plain path: 64
+    launches per step, and each cavity's own graph."""
     import tempfile
     from paper_1308_2071_amd import Batch, Cavity, workloads
     cav = workloads.batch64()
