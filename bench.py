@@ -343,8 +343,8 @@ def calib_copy(mib, torch):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(see the sharding design notes); rerun with --gpus 1", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(the sharding is a design only); rerun with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1308_2071_amd import workloads

@@ -46,7 +46,7 @@ typedef int32_t lbm_status;
 #define LBM_E_HIP (-3)         /* a HIP call failed (launch, copy, or an earlier async fault) */
 #define LBM_E_DIVERGED (-4)    /* a field is not finite or |u| exceeds cs; state still readable */
 #define LBM_E_STATE (-5)       /* call not valid in the context's current state             */
-#define LBM_E_UNSUPPORTED (-6) /* valid request this build does not implement               */
+#define LBM_E_UNSUPPORTED (-6) /* valid request the library does not implement             */
 
 /* Precision: storage of the populations, medium planes and fields, and the arithmetic of
  * every per-node operation.  LBM_FP32_F64 stores FP32 (the bytes of LBM_FP32) and computes each
