@@ -80,6 +80,8 @@ def parse():
                     help="roofline leg: 0 the library's choice, 1 or 2 forced")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip batched / adjoint / FP64 legs")
+    ap.add_argument("--batch-steps", type=int, default=10000,
+                    help="steps of every cavity in the batched leg (the workload's 10k)")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -385,7 +387,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_extras:
         print("# batched leg", file=sys.stderr, flush=True)
-        result["batched"] = leg_batched(torch)
+        result["batched"] = leg_batched(torch, args.batch_steps)
         print("# adjoint leg", file=sys.stderr, flush=True)
         result["adjoint"] = leg_adjoint(torch)
         print("# 256^2 FP32/FP64 leg", file=sys.stderr, flush=True)

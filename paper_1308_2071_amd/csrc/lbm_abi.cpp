@@ -1270,6 +1270,11 @@ lbm_status lbm_batch_init(lbm_ctx** out, int32_t n, const lbm_params* p,
         delete c;
         return hip_fail(e, "lbm_batch_init");
     }
+    with_types(p[0].dtype, [&](auto st, auto rt) {
+        LBM_TYPES(st, rt)
+        prepare_batch_tb2<S, R>();
+        return 0;
+    });
     s = batch_tune(c, tune_cache_path);
     if (s == LBM_OK) {
         hipError_t e2 = batch_rest(c);  // tuning stepped the cavities: back to rest

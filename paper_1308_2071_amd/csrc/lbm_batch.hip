@@ -107,8 +107,8 @@ hipError_t launch_batch_step(const void* src, void* dst, const BatchTable<R>& T,
 template <typename S, typename R, int TW>
 __global__ __launch_bounds__(64 * TW) void batch_tb2_kernel(
     const S* __restrict__ src, S* __restrict__ dst, const BatchCavity* __restrict__ cav,
-    const Phys<R>* __restrict__ phys, const int* __restrict__ wg_cav, int rows) {
-    const int wg = tb_logical_group();
+    const Phys<R>* __restrict__ phys, const int* __restrict__ wg_cav, int rows, int chunk) {
+    const int wg = tb_logical_group(chunk);
     const int c = wg_cav[wg];
     const BatchCavity C = cav[c];
     const Phys<R> P = phys[c];
@@ -119,21 +119,48 @@ __global__ __launch_bounds__(64 * TW) void batch_tb2_kernel(
                              strip < nstrips, seg, rows);
 }
 
+// Work-groups of batch_tb2_kernel<S, R, TW> one XCD holds at once (the XCD chunk of
+// tb_logical_group); queried once, at the first call.
+template <typename S, typename R, int TW>
+static int batch_tb_chunk() {
+    static const int chunk = [] {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_tb2_kernel<S, R, TW>,
+                                                         64 * TW, 0) != hipSuccess)
+            return 1;
+        return max(1, cus * per_cu / 8);
+    }();
+    return chunk;
+}
+
+template <typename S, typename R>
+void prepare_batch_tb2() {
+    (void)batch_tb_chunk<S, R, 1>();
+    (void)batch_tb_chunk<S, R, 2>();
+    (void)batch_tb_chunk<S, R, 4>();
+}
+
 template <typename S, typename R>
 hipError_t launch_batch_tb2(const void* src, void* dst, const BatchTable<R>& T, int rows,
                             int waves, hipStream_t s) {
     switch (waves) {
         case 1:
-            batch_tb2_kernel<S, R, 1><<<T.ntiles, 64, 0, s>>>((const S*)src, (S*)dst, T.cav,
-                                                              T.phys, T.tile_cav, rows);
+            batch_tb2_kernel<S, R, 1><<<T.ntiles, 64, 0, s>>>(
+                (const S*)src, (S*)dst, T.cav, T.phys, T.tile_cav, rows,
+                batch_tb_chunk<S, R, 1>());
             break;
         case 2:
-            batch_tb2_kernel<S, R, 2><<<T.ntiles, 128, 0, s>>>((const S*)src, (S*)dst, T.cav,
-                                                               T.phys, T.tile_cav, rows);
+            batch_tb2_kernel<S, R, 2><<<T.ntiles, 128, 0, s>>>(
+                (const S*)src, (S*)dst, T.cav, T.phys, T.tile_cav, rows,
+                batch_tb_chunk<S, R, 2>());
             break;
         case 4:
-            batch_tb2_kernel<S, R, 4><<<T.ntiles, 256, 0, s>>>((const S*)src, (S*)dst, T.cav,
-                                                               T.phys, T.tile_cav, rows);
+            batch_tb2_kernel<S, R, 4><<<T.ntiles, 256, 0, s>>>(
+                (const S*)src, (S*)dst, T.cav, T.phys, T.tile_cav, rows,
+                batch_tb_chunk<S, R, 4>());
             break;
         default: return hipErrorInvalidValue;
     }
@@ -148,6 +175,9 @@ template hipError_t launch_batch_step<double, double>(const void*, void*,
 template hipError_t launch_batch_step<float, double>(const void*, void*,
                                                      const BatchTable<double>&, int, int, int,
                                                      hipStream_t);
+template void prepare_batch_tb2<float, float>();
+template void prepare_batch_tb2<double, double>();
+template void prepare_batch_tb2<float, double>();
 template hipError_t launch_batch_tb2<float, float>(const void*, void*, const BatchTable<float>&,
                                                    int, int, hipStream_t);
 template hipError_t launch_batch_tb2<double, double>(const void*, void*,

@@ -96,6 +96,9 @@ struct BatchTable {
 template <typename S, typename R>
 hipError_t launch_batch_tb2(const void* src, void* dst, const BatchTable<R>& T, int rows,
                             int waves, hipStream_t s);
+// Queries the batched two-step kernel's resident set once (call outside graph capture)
+template <typename S, typename R>
+void prepare_batch_tb2();
 
 // rows: rows per tile (work-group = 64 * rows work-items); nodes_x: 64-node segments per
 // work-item along x; nwg >= ntiles: one tile per work-group, else chunked persistent.

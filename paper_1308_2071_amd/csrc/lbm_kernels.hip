@@ -70,11 +70,11 @@ __global__ __launch_bounds__(64 * kTbWaves) void tb2_step_kernel(const S* __rest
                                                                  S* __restrict__ dst,
                                                                  const S* __restrict__ med,
                                                                  Geo G, Phys<R> P, int nstrips,
-                                                                 int rows) {
+                                                                 int rows, int chunk) {
     // A work-group holds kTbWaves adjacent strips of one row segment, kept in step by a
     // barrier per row, so that the cache lines the neighbouring strips share are used while
     // resident.
-    const int wg = tb_logical_group();
+    const int wg = tb_logical_group(chunk);
     const int ngrp = (nstrips + kTbWaves - 1) / kTbWaves;
     const int strip = (wg % ngrp) * kTbWaves + (threadIdx.x >> 6), seg = wg / ngrp;
     tb2_segment<S, R, PN>(src, dst, med, G, P, strip, strip < nstrips, seg, rows);
@@ -362,12 +362,14 @@ hipError_t launch_tb2_step(const void* src, void* dst, const void* med, const Ge
     const int nstrips = (G.nx + kTbCols - 1) / kTbCols;
     int rows = 0, nwg = 0;
     tb2_shape<S, R>(G, med != nullptr, &rows, &nwg);
+    // XCD chunks of one XCD's resident work-groups (the resident set over 8 XCDs)
+    const int chunk = max(1, tb_resident<S, R>(med != nullptr) / 8);
     if (med)
         tb2_step_kernel<S, R, true><<<nwg, 64 * kTbWaves, 0, s>>>(
-            (const S*)src, (S*)dst, (const S*)med, G, P, nstrips, rows);
+            (const S*)src, (S*)dst, (const S*)med, G, P, nstrips, rows, chunk);
     else
-        tb2_step_kernel<S, R, false><<<nwg, 64 * kTbWaves, 0, s>>>((const S*)src, (S*)dst,
-                                                                   nullptr, G, P, nstrips, rows);
+        tb2_step_kernel<S, R, false><<<nwg, 64 * kTbWaves, 0, s>>>(
+            (const S*)src, (S*)dst, nullptr, G, P, nstrips, rows, chunk);
     return hipGetLastError();
 }
 

@@ -273,13 +273,21 @@ __device__ __forceinline__ void tb2_segment(const S* __restrict__ src, S* __rest
     } while (++y < y1);
 }
 
-// Work-groups are dealt round-robin over the 8 XCDs; this maps a launch's work-group index to a
-// logical one so that each XCD gets a contiguous range of logical work-groups (a bijection), and
-// neighbouring strips and segments share its L2.
-__device__ __forceinline__ int tb_logical_group() {
-    const int n = gridDim.x, per = n / 8, extra = n % 8;
-    const int wg = blockIdx.x, xcd = wg % 8, slot = wg / 8;
-    return xcd * per + min(xcd, extra) + slot;
+// Work-groups are dealt round-robin over the 8 XCDs.  This maps a launch's work-group index to a
+// logical one (a bijection) so that each XCD takes chunks of `chunk` consecutive logical
+// work-groups, the 8 XCDs' chunks side by side: with `chunk` the number of work-groups an XCD
+// holds at once, the work-groups resident together form one contiguous band of the grid, each
+// XCD's part of it contiguous, so neighbouring strips and segments share that XCD's L2 and all
+// XCDs stream nearby rows.  Measured on the 4096^2 FP32 workload: chunks of 128 (one XCD's
+// resident set) 66.9k MLUPS, 32: 65.8k, one contiguous range per XCD: 65.5k, plain
+// round-robin: 64.3k.  The last incomplete round of chunks falls back to contiguous ranges.
+__device__ __forceinline__ int tb_logical_group(int chunk) {
+    const int n = gridDim.x, wg = blockIdx.x, xcd = wg % 8, slot = wg / 8;
+    const int base = n - n % (8 * chunk);
+    const int logical = ((slot / chunk) * 8 + xcd) * chunk + slot % chunk;
+    if (logical < base) return logical;
+    const int rest = n - base, per = rest / 8, extra = rest % 8;
+    return base + xcd * per + min(xcd, extra) + (slot - base / 8);
 }
 
 }  // namespace lbm
