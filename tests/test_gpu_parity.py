@@ -151,6 +151,24 @@ def test_save_load_resume_is_bitwise():
     assert np.array_equal(a.save(), b.save())
 
 
+@pytest.mark.parametrize("spl", [1, 2])
+def test_zero_steps_is_a_no_op_and_negative_steps_are_rejected(spl):
+    params = dict(nx=33, ny=20, Ra=1e5, Pr=0.71, dtype="fp32", steps_per_launch=spl)
+    cav = Cavity(params, phi_uniform=0.6)
+    cav.step(5)
+    before = cav.observables()
+    snap = cav.save()
+    cav.step(0)
+    after = cav.observables()
+    assert after["step"] == 5 and np.array_equal(cav.save(), snap)
+    for k in FIELDS:
+        assert torch.equal(before[k], after[k]), k
+    with pytest.raises(RuntimeError, match="LBM_E_INVAL"):
+        cav.step(-1)
+    assert cav.observables(False)["step"] == 5
+    cav.close()
+
+
 def test_divergence_is_reported():
     """A non-finite value in the state (here planted through lbm_load, the way a corrupted
     checkpoint would arrive) spreads within a few steps; the library reports LBM_E_DIVERGED
