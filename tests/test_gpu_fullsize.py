@@ -145,6 +145,25 @@ def test_roofline4096_fused_equals_single_steps_over_1000_steps(dtype):
     single.close()
 
 
+def test_fp64_4096_fused_state_near_the_2_gib_limit_equals_single_steps():
+    """FP64 at 4096^2 holds 1.88 GB per state, close to the 2 GiB the two-step kernel's buffer
+    descriptors allow: the largest scalar offsets (plane 13 of the last rows) and the dropped
+    stores of halo lanes (2 GiB past them) are exercised.  Fused equals single steps bitwise,
+    with an odd step count."""
+    w = workloads.roofline4096()
+    phi, K = torch.from_numpy(w["phi"]), torch.from_numpy(w["K"])
+    fused = Cavity(dict(w["params"], dtype="fp64", steps_per_launch=2), phi=phi, K=K)
+    single = Cavity(dict(w["params"], dtype="fp64", steps_per_launch=1), phi=phi, K=K)
+    fused.step(101)
+    single.step(101)
+    a, b = fused.observables(), single.observables()
+    for k in FIELDS:
+        assert torch.equal(a[k], b[k]), k
+    assert a["nu_hot"] == b["nu_hot"]
+    fused.close()
+    single.close()
+
+
 # adjoint: gradient field vs the oracle adjoint (of max |grad|), J, and probes vs the Richardson
 # finite differences (of max |dJ/deps|; the differences themselves carry ~1e-5)
 ADJ_TOL = {"fp32": (1e-3, 1e-3, 1e-3), "fp32_f64": (1e-4, 1e-4, 1e-4), "fp64": (1e-8, 1e-10, 3e-5)}
