@@ -3,10 +3,11 @@ inputs: u_x, u_y, p, T at every node and the two wall Nusselt numbers (Eq. (38))
 
 Tolerances: FP64 max-abs 1e-12 after short runs on tiny grids and 1e-10 after the 20k steps of
 the 64 x 64 cavity; FP32 1e-4 of each field's range (range = max - min of the oracle's field)
-and Nu within 1e-3; FP32 storage with FP64 arithmetic ("fp32_f64") 1e-5 and 1e-4.  p is the pressure of Eq. (23) less its rest value rho0 cs^2 / phi, as the
-library reports it (the oracle's p is converted in FP64).  FP32 compares p up to a constant:
-the density is fixed at rho0, only pressure differences enter the momentum equation and nothing
-pins the level, which rounding moves.  In the first steps a field's range can be far below its
+and Nu within 1e-3; FP32 storage with FP64 arithmetic ("fp32_f64") 1e-5 and 1e-4.  p is the
+pressure of Eq. (23) less its rest value rho0 cs^2 / phi, as the library reports it (the
+oracle's p is converted in FP64).  FP32 compares p up to a constant: the density is fixed at
+rho0, only pressure differences enter the momentum equation and nothing pins the level, which
+rounding moves.  In the first steps a field's range can be far below its
 magnitude; there the range is floored at 1e-2 of the field's magnitude, so the bar never drops
 below ~15 FP32 ulps of the value.  For FP32-storage runs the oracle receives the FP32-rounded
 phi and K, so only the arithmetic and the storage differ.
