@@ -164,6 +164,33 @@ def test_fp64_4096_fused_state_near_the_2_gib_limit_equals_single_steps():
     single.close()
 
 
+def test_largest_grid_the_state_limit_allows_fp64_against_oracle():
+    """The largest square grid under the 2^31-element state limit (12352^2, 14 planes of
+    152.6M nodes; FP64 planes of 1.22 GB, the largest 32-bit byte offsets any kernel forms),
+    uniform medium, two steps: every node against the FP64 oracle at 1e-12."""
+    n = 12352
+    params = workloads.cavity(n, Ra=1e6, Pr=0.71, Da=1e-3)
+    cav = Cavity(dict(params, dtype="fp64"), phi_uniform=0.6)
+    cav.step(2)
+    g = cav.observables()
+    cav.close()
+    ref.set_threads(len(os.sched_getaffinity(0)))
+    lat = ref.RefLattice(phi_uniform=0.6, **params)
+    lat.step(2)
+    r = lat.observables(dynamic_pressure=True)
+    lat.close()
+    for k in FIELDS:
+        a = g[k].cpu().numpy()
+        assert a.shape == (n, n)
+        err = np.abs(a - r[k]).max()
+        assert err <= 1e-12, (k, err)
+        del a
+    # Nu = -L D / dT with L = n - 1: two steps from rest give Nu ~ 1e3-1e4 here, so the bar is
+    # relative (a 1e-16 relative rounding of D becomes ~1e-12 of Nu after the trapezoid sum)
+    for k in ("nu_hot", "nu_cold"):
+        assert abs(g[k] - r[k]) <= 1e-12 * max(1.0, abs(r[k])), (k, g[k], r[k])
+
+
 # adjoint: gradient field vs the oracle adjoint (of max |grad|), J, and probes vs the Richardson
 # finite differences (of max |dJ/deps|; the differences themselves carry ~1e-5)
 ADJ_TOL = {"fp32": (1e-3, 1e-3, 1e-3), "fp32_f64": (1e-4, 1e-4, 1e-4), "fp64": (1e-8, 1e-10, 3e-5)}
