@@ -8,6 +8,11 @@
 - roofline4096 (4096 x 4096, per-node phi and K, FP32 storage with FP32 or FP64 arithmetic): the
   first 10 steps against the oracle on the full field, and a 512 x 512 crop of the same medium
   for 2000 steps (FP64 arithmetic on FP32 storage is held to 1e-5 of range and Nu to 1e-4);
+- the largest square grid the 2^31-element state limit allows (12352^2, FP64): two steps
+  against the oracle at every node;
+- two steps per launch at full size: bitwise equal to single steps over 1000 steps of the
+  roofline4096 field (FP32 and FP64 arithmetic), and for FP64 storage at 4096^2, a state near
+  the two-step kernel's 2 GiB limit;
 - adjoint256 (256 x 256, 2000 steps, checkpoint every 100): the HIP adjoint's dJ/deps at 16
   probes against central FP64 finite differences of the oracle (FP32 within 1e-3 of max |grad|,
   FP64 arithmetic on FP32 storage 1e-4, FP64 within the differences' own 3e-5), and dJ/dphi,
