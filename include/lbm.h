@@ -44,7 +44,7 @@ typedef int32_t lbm_status;
 #define LBM_E_INVAL (-1)       /* bad argument; nothing was enqueued                        */
 #define LBM_E_NOMEM (-2)       /* workspace too small, or host allocation failed            */
 #define LBM_E_HIP (-3)         /* a HIP call failed (launch, copy, or an earlier async fault) */
-#define LBM_E_DIVERGED (-4)    /* a field is not finite or |u| exceeds cs; state still readable */
+#define LBM_E_DIVERGED (-4)    /* the run diverged (see lbm_obs.why); state still readable   */
 #define LBM_E_STATE (-5)       /* call not valid in the context's current state             */
 #define LBM_E_UNSUPPORTED (-6) /* valid request the library does not implement             */
 
@@ -108,6 +108,22 @@ typedef struct {
                              /* gives LBM_E_UNSUPPORTED, 0 steps one at a time.               */
 } lbm_params;
 
+/* Reasons for the divergence flag (bits of lbm_obs.why).  The paper gives no divergence test;
+ * these are the library's. */
+#define LBM_DIV_NONFINITE 1    /* u, p, T, Nu or |v| of Eq. (22) is not finite (once |v|^2    */
+                               /* overflows, Eq. (21) gives u = 0, so u alone cannot show it) */
+#define LBM_DIV_SPEED 2        /* max |u| exceeds cs = 1/sqrt(3) (Ma above 1)                */
+#define LBM_DIV_TEMPERATURE 4  /* T leaves [T_lo - dT - r_lo, T_hi + dT + r_hi]: T_lo, T_hi   */
+                               /* the min and max of T_init and the isothermal walls' T, dT  */
+                               /* the temperature scale (out[6] of lbm_derived), r the rise   */
+                               /* a heat source Q can cause, in the bound of its sign only:  */
+                               /* |Q| Lmax^2 / (2 alpha_e), Lmax = max(nx, ny) - 1, when some */
+                               /* side is isothermal (conduction alpha_e T'' = -Q from one    */
+                               /* isothermal side), else |Q| n / sigma (Eq. (3) with no heat  */
+                               /* leaving); alpha_e = sigma csT^2 (tau_T - 1/2), Eq. (A9)     */
+#define LBM_DIV_PRESSURE 8     /* phi p leaves (0, 2 rho0 cs^2): |phi p - rho0 cs^2| exceeds  */
+                               /* the rest value rho0 cs^2 (Eq. (23))                        */
+
 /* Observables at the current time level. */
 typedef struct {
     double nu_hot;    /* average Nusselt number of the west wall, Eq. (38)                     */
@@ -115,8 +131,11 @@ typedef struct {
     double max_speed; /* max |u| over the lattice                                              */
     double mass_err;  /* |sum f - n rho0| / (n rho0) over the stored post-collision populations */
     int64_t step;     /* time level n                                                          */
-    int32_t diverged; /* 1 when a field is not finite or max |u| exceeds cs = 1/sqrt(3)        */
-    int32_t pad_;
+    int32_t diverged; /* 1 when any LBM_DIV_* condition holds                                  */
+    int32_t why;      /* the LBM_DIV_* bits that hold (0 when not diverged)                    */
+    double T_min;     /* min T over the lattice (Eq. (36))                                     */
+    double T_max;     /* max T over the lattice                                                */
+    double phip_dev;  /* max |phi p - rho0 cs^2| over the lattice (Eq. (23))                   */
 } lbm_obs;
 
 typedef struct lbm_ctx lbm_ctx;
@@ -160,7 +179,8 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps);
  * arrays [ny][nx] of the context's dtype receiving u (Eq. (21)), the dynamic pressure
  * p - rho0 cs^2 / phi (p of Eq. (23) less its rest value, which FP32 could not carry the
  * dynamic part on top of; at wall nodes phi_b p_b = phi_f p_f), T (Eq. (36)).  Returns
- * LBM_E_DIVERGED with o->diverged = 1 when a field is not finite or max |u| exceeds cs. */
+ * LBM_E_DIVERGED with o->diverged = 1 and the reasons in o->why (LBM_DIV_*) when the run
+ * diverged. */
 lbm_status lbm_observables(lbm_ctx* c, lbm_obs* o, void* ux, void* uy, void* p, void* T);
 
 /* Stream function at the current time level (synchronises): psi (device array [ny][nx] of the
@@ -216,7 +236,8 @@ lbm_status lbm_batch_init(lbm_ctx** out, int32_t n, const lbm_params* p,
 /* Advance every cavity by nsteps (asynchronous; replayed from a captured HIP graph). */
 lbm_status lbm_batch_step(lbm_ctx* c, int64_t nsteps);
 
-/* Observables of every cavity (synchronises); o has n entries. */
+/* Observables of every cavity (synchronises); o has n entries.  Returns LBM_E_DIVERGED when
+ * any cavity diverged; each entry's diverged and why say which (as in lbm_observables). */
 lbm_status lbm_batch_observables(lbm_ctx* c, lbm_obs* o);
 
 /* Macroscopic fields of cavity i at the current time level (synchronises): optional device

@@ -292,6 +292,7 @@ static void neq(double T, double ux, double uy, double sigma, double varpi, doub
 /* Macroscopic state of one node. */
 typedef struct {
     double T, ux, uy, phip, Fx, Fy, phi;
+    double vv;   /* |v|^2 of Eq. (22) (a wall node carries its inward neighbour's) */
 } macro_t;
 
 /* Eqs. (36), (22), (21), (23), (4) for a fluid node from its post-streaming populations. */
@@ -328,6 +329,7 @@ static void interior_macros(const double fh[9], const double gh[5], double phi, 
     m->Fx = -phi * d->nu / K * ux - phi * Fphi / sqrt(K) * umag * ux + phi * Gx; /* Eq. (4) */
     m->Fy = -phi * d->nu / K * uy - phi * Fphi / sqrt(K) * umag * uy + phi * Gy;
     m->phi = phi;
+    m->vv = vx * vx + vy * vy;
 }
 
 /* Eq. (17) then Eq. (34) at one node: post-streaming populations -> post-collision ones. */
@@ -511,6 +513,7 @@ static void macros_and_walls(ref_ctx *c) {
             mb->uy = 0.0;
             mb->phip = mf->phip;           /* phi_b p_b = phi_f p_f */
             mb->phi = phib;
+            mb->vv = mf->vv;
             mb->Fx = phib * p->ext_accel[0];
             mb->Fy = phib * (p->ext_accel[1] + d->gbeta * (Tb - d->T0));
             /* f_b = f^eq(wall) + [f(x_f) - f^eq(x_f)], likewise for g */
@@ -554,17 +557,47 @@ void ref_step(ref_ctx *c, int64_t nsteps) {
     }
 }
 
+/* Temperature interval outside which a run counts as diverged: [lo, hi] over T_init and the
+ * isothermal walls, widened by the temperature scale dT and, with a heat source, by what the
+ * source can add: |Q| Lmax^2 / (2 alpha_e) (conduction from one isothermal side across the
+ * longer side, alpha_e T'' = -Q) when some side is isothermal, else |Q| t / sigma (Eq. (3)
+ * with no heat leaving), Q the source Q''' of Eq. (30).  out[0] = lower, out[1] = upper. */
+static void temperature_bounds(const ref_ctx *c, double out[2]) {
+    const ref_params *p = &c->p;
+    const ref_derived *d = &c->d;
+    double lo = p->T_init, hi = p->T_init;
+    int iso = 0;
+    for (int s = 0; s < 4; ++s) {
+        if (p->bc[s] != REF_ISOTHERMAL) continue;
+        iso = 1;
+        if (p->T_wall[s] < lo) lo = p->T_wall[s];
+        if (p->T_wall[s] > hi) hi = p->T_wall[s];
+    }
+    const double Lmax = (double)((c->nx > c->ny ? c->nx : c->ny) - 1);
+    const double alpha = p->sigma * d->csT2 * (d->tau_T - 0.5);
+    const double rise = iso ? fabs(d->Q) * Lmax * Lmax / (2.0 * alpha)
+                            : fabs(d->Q) * (double)c->step / p->sigma;
+    out[0] = lo - fabs(d->dT) - (d->Q < 0 ? rise : 0.0);
+    out[1] = hi + fabs(d->dT) + (d->Q > 0 ? rise : 0.0);
+}
+
 /* Observables at the current time level: u, phi*p/phi, T per node ([ny][nx], any may be NULL)
- * and out[0..4] = Nu_hot (west wall), Nu_cold (east wall), max |u|, relative total-mass error
- * of the stored post-collision populations, and a divergence flag (1 when any field is not
- * finite or max |u| exceeds cs). */
+ * and out[0..7] = Nu_hot (west wall), Nu_cold (east wall), max |u|, relative total-mass error
+ * of the stored post-collision populations, a divergence flag, min T, max T and
+ * max |phi p - rho0 cs^2|.  The flag is 1 when
+ *   - a field (u, p, T) or |v| of Eq. (22) is not finite (|v|^2 overflowing makes the
+ *     denominator of Eq. (21) infinite and u = 0, so u alone cannot show it),
+ *   - max |u| exceeds cs,
+ *   - T leaves the interval of temperature_bounds, or
+ *   - phi p leaves (0, 2 rho0 cs^2), i.e. |phi p - rho0 cs^2| exceeds its rest value. */
 void ref_observables(ref_ctx *c, double *ux, double *uy, double *pr, double *T, double *out) {
     stream(c);
     macros_and_walls(c);
     const int nx = c->nx, ny = c->ny;
     const size_t n = c->n;
-    double umax = 0.0;
+    double umax = 0.0, tmin = INFINITY, tmax = -INFINITY, pdev = 0.0;
     int bad = 0;
+    const double prest = c->p.rho0 * c->d.cs2;
     for (size_t k = 0; k < n; ++k) {
         const macro_t *m = &c->mac[k];
         if (ux) ux[k] = m->ux;
@@ -573,7 +606,13 @@ void ref_observables(ref_ctx *c, double *ux, double *uy, double *pr, double *T, 
         if (T) T[k] = m->T;
         const double um = sqrt(m->ux * m->ux + m->uy * m->uy);
         if (!(um <= umax)) umax = um;
-        if (!isfinite(m->ux) || !isfinite(m->uy) || !isfinite(m->phip) || !isfinite(m->T)) bad = 1;
+        if (!isfinite(m->ux) || !isfinite(m->uy) || !isfinite(m->phip) || !isfinite(m->T) ||
+            !isfinite(m->vv))
+            bad = 1;
+        if (!(m->T >= tmin)) tmin = m->T;
+        if (!(m->T <= tmax)) tmax = m->T;
+        const double pd = fabs(m->phip - prest);
+        if (!(pd <= pdev)) pdev = pd;
     }
     /* Eq. (38) with the five-point one-sided derivative and the trapezoid rule. */
     double nu_h = 0.0, nu_c = 0.0;
@@ -600,7 +639,15 @@ void ref_observables(ref_ctx *c, double *ux, double *uy, double *pr, double *T, 
     out[1] = nu_c;
     out[2] = umax;
     out[3] = fabs(mass - mass_ref) / mass_ref;
-    out[4] = (bad || !(umax <= sqrt(c->d.cs2))) ? 1.0 : 0.0;
+    double tb[2];
+    temperature_bounds(c, tb);
+    out[4] = (bad || !(umax <= sqrt(c->d.cs2)) || !(tmin >= tb[0]) || !(tmax <= tb[1]) ||
+              !(pdev <= prest))
+                 ? 1.0
+                 : 0.0;
+    out[5] = tmin;
+    out[6] = tmax;
+    out[7] = pdev;
 }
 
 int64_t ref_get_step(const ref_ctx *c) { return c->step; }

@@ -181,16 +181,20 @@ class RefLattice:
 
     def observables(self, dynamic_pressure: bool = False) -> dict:
         """Fields u_x, u_y, p (Eq. (23)), T (Eq. (36)) and Nu_hot, Nu_cold (Eq. (38)); with
-        ``dynamic_pressure`` p less its rest value rho0 cs^2 / phi (cs^2 = 1/3), node by node."""
+        ``dynamic_pressure`` p less its rest value rho0 cs^2 / phi (cs^2 = 1/3), node by node.
+        Also max |u|, the mass deviation, min and max T, max |phi p - rho0 cs^2| and the
+        divergence flag (non-finite u, p, T or |v|; |u| > cs; T outside the bounds of the
+        walls, T_init and the heat source widened by dT; phi p outside (0, 2 rho0 cs^2))."""
         shp = (self.ny, self.nx)
         ux, uy, p, T = (np.empty(shp) for _ in range(4))
-        out = np.zeros(5)
+        out = np.zeros(8)
         lib().ref_observables(self._h, _ptr(ux), _ptr(uy), _ptr(p), _ptr(T), _ptr(out))
         if dynamic_pressure:
             phi = self._phi if self._phi is not None else self._phi_uniform
             p = p - self.params["rho0"] / 3.0 / phi
         return dict(ux=ux, uy=uy, p=p, T=T, nu_hot=out[0], nu_cold=out[1], max_speed=out[2],
-                    mass_err=out[3], diverged=bool(out[4]))
+                    mass_err=out[3], diverged=bool(out[4]), T_min=out[5], T_max=out[6],
+                    phip_dev_max=out[7])
 
     def get_state(self):
         f = np.empty((9, self.ny, self.nx))

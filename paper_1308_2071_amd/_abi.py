@@ -15,6 +15,7 @@ LBM_E_DIVERGED, LBM_E_STATE, LBM_E_UNSUPPORTED = -4, -5, -6
 LBM_FP32, LBM_FP64, LBM_FP32_F64 = 0, 1, 2
 LBM_LAYOUT_PULL, LBM_LAYOUT_AA = 0, 1
 LBM_WALL_ISOTHERMAL, LBM_WALL_ADIABATIC, LBM_PERIODIC = 0, 1, 2
+LBM_DIV_NONFINITE, LBM_DIV_SPEED, LBM_DIV_TEMPERATURE, LBM_DIV_PRESSURE = 1, 2, 4, 8
 
 
 class LbmParams(C.Structure):
@@ -43,7 +44,8 @@ class LbmObs(C.Structure):
     _fields_ = [
         ("nu_hot", C.c_double), ("nu_cold", C.c_double), ("max_speed", C.c_double),
         ("mass_err", C.c_double), ("step", C.c_int64), ("diverged", C.c_int32),
-        ("pad_", C.c_int32),
+        ("why", C.c_int32), ("T_min", C.c_double), ("T_max", C.c_double),
+        ("phip_dev", C.c_double),
     ]
 
 

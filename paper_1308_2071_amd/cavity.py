@@ -20,7 +20,8 @@ def _torch_dtype(p: LbmParams):
 
 def _obs_dict(o, status=LBM_OK) -> dict:
     return dict(nu_hot=o.nu_hot, nu_cold=o.nu_cold, max_speed=o.max_speed, mass_err=o.mass_err,
-                step=o.step, diverged=bool(o.diverged), status=status)
+                step=o.step, diverged=bool(o.diverged), why=int(o.why), T_min=o.T_min,
+                T_max=o.T_max, phip_dev=o.phip_dev, status=status)
 
 
 class Cavity:
@@ -56,7 +57,8 @@ class Cavity:
         return self
 
     def observables(self, fields: bool = True) -> dict:
-        """Nu_hot, Nu_cold (Eq. (38)), max |u|, mass deviation, step, diverged; with
+        """Nu_hot, Nu_cold (Eq. (38)), max |u|, mass deviation, step, min and max T,
+        max |phi p - rho0 cs^2|, the divergence flag and its reasons (LBM_DIV_* bits); with
         ``fields`` also u_x, u_y, the dynamic pressure p - rho0 cs^2 / phi and T as [ny][nx]
         tensors of the cavity's dtype."""
         if fields:

@@ -80,6 +80,52 @@ Derived derive(const lbm_params& p) {
 
 bool walled(const lbm_params& p, int side) { return p.bc[side] != LBM_PERIODIC; }
 
+// The interval T must stay in (LBM_DIV_TEMPERATURE): T_init and the isothermal walls' T,
+// widened by the temperature scale dT and by the rise the heat source can cause at step n.
+void temperature_bounds(const lbm_params& p, const Derived& d, int64_t n, double* lo,
+                        double* hi) {
+    double a = p.T_init, b = p.T_init;
+    bool iso = false;
+    for (int s = 0; s < 4; ++s)
+        if (p.bc[s] == LBM_WALL_ISOTHERMAL) {
+            iso = true;
+            a = std::min(a, p.T_wall[s]);
+            b = std::max(b, p.T_wall[s]);
+        }
+    const double Lmax = double(std::max(p.nx, p.ny) - 1);
+    const double alpha = p.sigma * d.csT2 * (d.tau_T - 0.5);  // Eq. (A9)
+    const double rise = iso ? std::fabs(d.Q) * Lmax * Lmax / (2.0 * alpha)
+                            : std::fabs(d.Q) * double(n) / p.sigma;
+    *lo = a - std::fabs(d.dT) - (d.Q < 0 ? rise : 0.0);
+    *hi = b + std::fabs(d.dT) + (d.Q > 0 ? rise : 0.0);
+}
+
+// Fills the observables from the results r[0 .. kObsOut) of the observables pass (Nu_hot,
+// Nu_cold, max |u|, sum f', non-finite flag, min T, max T, max |phi p - rho0 cs^2|) and
+// decides the divergence flag (LBM_DIV_* in lbm.h).
+void fill_obs(const lbm_params& p, const Derived& d, int64_t step, const double* r,
+              lbm_obs* o) {
+    const double n = double(p.nx) * p.ny;
+    o->nu_hot = r[0];
+    o->nu_cold = r[1];
+    o->max_speed = r[2];
+    o->mass_err = std::fabs(r[3]) / (n * p.rho0);
+    o->step = step;
+    o->T_min = r[5];
+    o->T_max = r[6];
+    o->phip_dev = r[7];
+    double lo, hi;
+    temperature_bounds(p, d, step, &lo, &hi);
+    const double prest = p.rho0 * d.cs2;
+    int why = 0;
+    if (r[4] != 0.0 || !std::isfinite(r[0]) || !std::isfinite(r[1])) why |= LBM_DIV_NONFINITE;
+    if (!(r[2] <= std::sqrt(d.cs2))) why |= LBM_DIV_SPEED;
+    if (!(r[5] >= lo) || !(r[6] <= hi)) why |= LBM_DIV_TEMPERATURE;
+    if (!(r[7] <= prest)) why |= LBM_DIV_PRESSURE;
+    o->why = why;
+    o->diverged = why != 0 ? 1 : 0;
+}
+
 // Bytes per stored value (populations, medium planes, fields) of a dtype.
 size_t storage_bytes(int dtype) { return dtype == LBM_FP64 ? 8 : 4; }
 
@@ -219,7 +265,7 @@ Layout make_layout(const lbm_params& p, int64_t nsteps_max, bool med_planes) {
     L.off_med = o;
     if (med_planes) o += align_up(2 * size_t(G.plane) * esz);
     L.off_part = o;
-    o += align_up((3 * kObserveWG + 16) * sizeof(double));
+    o += align_up((kObsParts * kObserveWG + kObsOut) * sizeof(double));
     L.off_tape = o;
     if (p.checkpoint_every > 0) {
         const size_t C = size_t(p.checkpoint_every);
@@ -420,6 +466,7 @@ namespace {
 
 constexpr int kBatchGraphSteps = 32;   // even: a replay ends on the buffer it started from
 constexpr int kBatchObsWG = 64;        // work-groups of one cavity's observables pass
+constexpr int kBatchObsPer = kObsParts * kBatchObsWG + kObsOut;  // doubles per cavity
 constexpr int kMinTileWidth = 64;      // narrowest tile of any supported launch shape
 
 struct BatchLayout {
@@ -487,7 +534,7 @@ lbm_status batch_layout(int32_t n, const lbm_params* p, BatchLayout* L) {
     L->max_tbwg = batch_tb_groups(geos, kTbMinRows, 1);   // the most: shortest rows, 1 strip
     o += align_up(L->max_tbwg * sizeof(int));
     L->off_part = o;
-    o += align_up(size_t(n) * (3 * kBatchObsWG + 8) * sizeof(double));
+    o += align_up(size_t(n) * kBatchObsPer * sizeof(double));
     L->total = o;
     return LBM_OK;
 }
@@ -1008,7 +1055,7 @@ lbm_status lbm_observables(lbm_ctx* c, lbm_obs* o, void* ux, void* uy, void* p, 
     if (s != LBM_OK) return s;
     if (!o) return fail(LBM_E_INVAL, "null lbm_obs");
     double* part = c->part();
-    double* res = part + 3 * kObserveWG;
+    double* res = part + kObsParts * kObserveWG;
     const double LdT = c->d.L / c->d.dT;
     hipError_t e = with_types(c->p.dtype, [&](auto st, auto rt) {
         LBM_TYPES(st, rt)
@@ -1016,21 +1063,13 @@ lbm_status lbm_observables(lbm_ctx* c, lbm_obs* o, void* ux, void* uy, void* p, 
                                     ux, uy, p, T, part, kObserveWG, LdT, res, c->stream);
     });
     if (e != hipSuccess) return hip_fail(e, "observables launch");
-    double h[5];
+    double h[kObsOut];
     HIP_TRY(hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, c->stream), "readback");
     HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
-    const double n = double(c->p.nx) * c->p.ny;
-    o->nu_hot = h[0];
-    o->nu_cold = h[1];
-    o->max_speed = h[2];
-    o->mass_err = std::fabs(h[3]) / (n * c->p.rho0);
-    o->step = c->step;
-    o->diverged = (h[4] != 0.0 || !(h[2] <= std::sqrt(1.0 / 3.0)) || !std::isfinite(h[0]) ||
-                   !std::isfinite(h[1]))
-                      ? 1
-                      : 0;
-    o->pad_ = 0;
-    if (o->diverged) return fail(LBM_E_DIVERGED, "diverged at step %lld", (long long)c->step);
+    fill_obs(c->p, c->d, c->step, h, o);
+    if (o->diverged)
+        return fail(LBM_E_DIVERGED, "diverged at step %lld (reasons %d)", (long long)c->step,
+                    o->why);
     return LBM_OK;
 }
 
@@ -1327,12 +1366,12 @@ lbm_status lbm_batch_observables(lbm_ctx* c, lbm_obs* o) {
     const int n = c->ncav;
     const size_t esz = storage_bytes(c->p.dtype);
     double* part0 = (double*)(c->ws + c->b_off_part);
-    const size_t per = 3 * kBatchObsWG + 8;
+    const size_t per = kBatchObsPer;
     char* base = c->ws + c->b_off_buf[c->cur];
     for (int i = 0; i < n; ++i) {
         const void* src = base + size_t(c->boff[i]) * esz;
         double* part = part0 + i * per;
-        double* res = part + 3 * kBatchObsWG;
+        double* res = part + kObsParts * kBatchObsWG;
         hipError_t e = with_types(c->p.dtype, [&](auto st, auto rt) {
             LBM_TYPES(st, rt)
             return launch_observe<S, R>(src, nullptr, c->bG[i], bphys<R>(c, i), kPull, nullptr,
@@ -1348,17 +1387,8 @@ lbm_status lbm_batch_observables(lbm_ctx* c, lbm_obs* o) {
     HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
     bool any = false;
     for (int i = 0; i < n; ++i) {
-        const double* r = h.data() + i * per + 3 * kBatchObsWG;
-        const double nn = double(c->bp[i].nx) * c->bp[i].ny;
-        o[i].nu_hot = r[0];
-        o[i].nu_cold = r[1];
-        o[i].max_speed = r[2];
-        o[i].mass_err = std::fabs(r[3]) / (nn * c->bp[i].rho0);
-        o[i].step = c->step;
-        o[i].diverged = (r[4] != 0.0 || !(r[2] <= std::sqrt(1.0 / 3.0)) || !std::isfinite(r[0]))
-                            ? 1
-                            : 0;
-        o[i].pad_ = 0;
+        const double* r = h.data() + i * per + kObsParts * kBatchObsWG;
+        fill_obs(c->bp[i], derive(c->bp[i]), c->step, r, &o[i]);
         any = any || o[i].diverged;
     }
     if (any) return fail(LBM_E_DIVERGED, "a cavity diverged at step %lld", (long long)c->step);
@@ -1371,8 +1401,8 @@ lbm_status lbm_batch_fields(lbm_ctx* c, int32_t i, void* ux, void* uy, void* p, 
     if (i < 0 || i >= c->ncav) return fail(LBM_E_INVAL, "cavity %d of %d", i, c->ncav);
     const size_t esz = storage_bytes(c->p.dtype);
     const void* src = c->ws + c->b_off_buf[c->cur] + size_t(c->boff[i]) * esz;
-    double* part = (double*)(c->ws + c->b_off_part) + size_t(i) * (3 * kBatchObsWG + 8);
-    double* res = part + 3 * kBatchObsWG;
+    double* part = (double*)(c->ws + c->b_off_part) + size_t(i) * kBatchObsPer;
+    double* res = part + kObsParts * kBatchObsWG;
     hipError_t e = with_types(c->p.dtype, [&](auto st, auto rt) {
         LBM_TYPES(st, rt)
         return launch_observe<S, R>(src, nullptr, c->bG[i], bphys<R>(c, i), kPull, ux, uy, p, T,

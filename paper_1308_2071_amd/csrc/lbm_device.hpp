@@ -80,10 +80,12 @@ struct Med {
     R phi, inv_phi, c_lin, c_nl;
 };
 
-// Macroscopic state of one node: theta = T - T0, u, P = phi p - rho0 cs^2, F (Eq. (4)).
+// Macroscopic state of one node: theta = T - T0, u, P = phi p - rho0 cs^2, F (Eq. (4)), and
+// |v|^2 of Eq. (22) (a wall node carries its inward neighbour's), which the divergence check
+// reads: once |v|^2 overflows, Eq. (21) returns u = 0 and u alone no longer shows the blow-up.
 template <typename R>
 struct Mac {
-    R theta, ux, uy, P, Fx, Fy;
+    R theta, ux, uy, P, Fx, Fy, vv;
 };
 
 __device__ __forceinline__ float rsq(float x) { return __frsqrt_rn(x); }
@@ -186,7 +188,8 @@ __device__ __forceinline__ Mac<R> fluid_macros(const R f[9], const R g[5], const
     const R vy = jy * P.inv_rho0 + hphi * Gy;
     const R l0 = R(0.5) + R(0.25) * md.c_lin;
     const R l1 = R(0.5) * md.c_nl;
-    const R vmag = sqrt(vx * vx + vy * vy);
+    const R vv = vx * vx + vy * vy;
+    const R vmag = sqrt(vv);
     // divide rather than multiply by a rounded reciprocal: in a uniform medium the denominator
     // is nearly the same at every node, so the reciprocal's rounding would act as one common
     // gain on the momentum, step after step
@@ -202,6 +205,7 @@ __device__ __forceinline__ Mac<R> fluid_macros(const R f[9], const R g[5], const
     m.uy = uy;
     m.Fx = md.phi * Gx - drag * ux;
     m.Fy = md.phi * Gy - drag * uy;
+    m.vv = vv;
     return m;
 }
 
@@ -358,6 +362,7 @@ __device__ __forceinline__ Mac<R> wall_state(bool onW, bool onE, bool onS, bool 
     m.P = mf.P;
     m.Fx = mdb.phi * P.ax;
     m.Fy = mdb.phi * (P.ay + P.gbeta * theta_b);
+    m.vv = mf.vv;
     return m;
 }
 

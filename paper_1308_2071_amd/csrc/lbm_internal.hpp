@@ -9,6 +9,8 @@ namespace lbm {
 
 constexpr int kTileX = 256;      // nodes (work-items) per work-group of the step kernel
 constexpr int kObserveWG = 512;  // work-groups of the observables pass
+constexpr int kObsParts = 6;     // partial results per work-group of the observables pass
+constexpr int kObsOut = 2 + kObsParts;  // results of the observables pass (Nu_hot, Nu_cold, ...)
 constexpr int kPitchAlign = 64;  // row pitch in elements
 // Two steps per launch: columns a wavefront's strip writes, strips per work-group, the number
 // of resident-set rounds the segment height aims for, and the shortest segment.

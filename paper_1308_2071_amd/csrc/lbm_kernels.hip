@@ -80,6 +80,15 @@ __global__ __launch_bounds__(64 * kTbWaves) void tb2_step_kernel(const S* __rest
     tb2_segment<S, R, PN>(src, dst, med, G, P, strip, strip < nstrips, seg, rows);
 }
 
+// Maximum and minimum that propagate a NaN (fmax and fmin would drop it), so that a
+// non-finite value always reaches the result of a reduction.
+__device__ __forceinline__ double obs_max(double a, double b) {
+    return (a >= b || a != a) ? a : b;
+}
+__device__ __forceinline__ double obs_min(double a, double b) {
+    return (a <= b || a != a) ? a : b;
+}
+
 // Wave-level reductions over the 64 lanes of a wavefront.
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -88,13 +97,19 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    for (int off = 32; off > 0; off >>= 1) v = obs_max(v, __shfl_down(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = obs_min(v, __shfl_down(v, off, 64));
     return v;
 }
 
-// Macroscopic fields at the current time level, plus per-work-group partial results:
-// part[3 * b + 0] = max |u|, part[3 * b + 1] = sum of stored f' (mass deviation),
-// part[3 * b + 2] = 1 if a field is not finite.  Grid-stride over nodes.
+// Macroscopic fields at the current time level, plus kObsParts partial results per
+// work-group b at part[kObsParts * b + k]: k = 0 max |u|, 1 the sum of stored f' (mass
+// deviation), 2 a flag (1 when u, p, T or |v| of Eq. (22) is not finite), 3 min T, 4 max T,
+// 5 max |phi p - rho0 cs^2|.  Grid-stride over nodes.
 template <typename S, typename R, bool PN, int L>
 __global__ __launch_bounds__(256) void observe_kernel(const S* __restrict__ src,
                                                       const S* __restrict__ med, Geo G,
@@ -104,7 +119,7 @@ __global__ __launch_bounds__(256) void observe_kernel(const S* __restrict__ src,
                                                       S* __restrict__ T_out,
                                                       double* __restrict__ part) {
     const int n = G.nx * G.ny;
-    double umax = 0.0, mass = 0.0, bad = 0.0;
+    double v[kObsParts] = {0.0, 0.0, 0.0, INFINITY, -INFINITY, 0.0};
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
         const int y = k / G.nx, x = k - y * G.nx;
         R f[9], g[5];
@@ -120,35 +135,46 @@ __global__ __launch_bounds__(256) void observe_kernel(const S* __restrict__ src,
         if (p_out) p_out[k] = S(p);
         if (T_out) T_out[k] = S(T);
         const double sp = sqrt(double(m.ux) * double(m.ux) + double(m.uy) * double(m.uy));
-        umax = fmax(umax, sp);
-        if (!isfinite(sp) || !isfinite(double(p)) || !isfinite(double(T))) bad = 1.0;
+        const double Td = double(T), Pd = fabs(double(m.P));
+        v[0] = obs_max(v[0], sp);
+        if (!isfinite(sp) || !isfinite(double(p)) || !isfinite(Td) || !isfinite(double(m.vv)))
+            v[2] = 1.0;
+        v[3] = obs_min(v[3], Td);
+        v[4] = obs_max(v[4], Td);
+        v[5] = obs_max(v[5], Pd);
         const int o = y * G.pitch + x;
         double s = 0.0;
 #pragma unroll
         for (int i = 0; i < 9; ++i) s += double(src[i * G.plane + o]);
-        mass += s;
+        v[1] += s;
     }
-    __shared__ double red[3][4];
-    umax = wave_max(umax);
-    mass = wave_sum(mass);
-    bad = wave_max(bad);
+    __shared__ double red[kObsParts][4];
+    v[0] = wave_max(v[0]);
+    v[1] = wave_sum(v[1]);
+    v[2] = wave_max(v[2]);
+    v[3] = wave_min(v[3]);
+    v[4] = wave_max(v[4]);
+    v[5] = wave_max(v[5]);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (lane == 0) {
-        red[0][w] = umax;
-        red[1][w] = mass;
-        red[2][w] = bad;
+#pragma unroll
+        for (int k = 0; k < kObsParts; ++k) red[k][w] = v[k];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double a = red[0][0], b = red[1][0], c = red[2][0];
+        double r[kObsParts];
+#pragma unroll
+        for (int k = 0; k < kObsParts; ++k) r[k] = red[k][0];
         for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
-            a = fmax(a, red[0][i]);
-            b += red[1][i];
-            c = fmax(c, red[2][i]);
+            r[0] = obs_max(r[0], red[0][i]);
+            r[1] += red[1][i];
+            r[2] = obs_max(r[2], red[2][i]);
+            r[3] = obs_min(r[3], red[3][i]);
+            r[4] = obs_max(r[4], red[4][i]);
+            r[5] = obs_max(r[5], red[5][i]);
         }
-        part[3 * blockIdx.x + 0] = a;
-        part[3 * blockIdx.x + 1] = b;
-        part[3 * blockIdx.x + 2] = c;
+#pragma unroll
+        for (int k = 0; k < kObsParts; ++k) part[kObsParts * blockIdx.x + k] = r[k];
     }
 }
 
@@ -171,9 +197,9 @@ __device__ __forceinline__ double node_theta(const S* __restrict__ src, const Ge
 
 // Eq. (38): Nu(y) = -L dT/dx / dT at the west (hot) and east (cold) walls with the
 // fourth-order one-sided five-point derivative, averaged by the trapezoid rule over the
-// ny wall nodes; part[0..2] = partial results of observe_kernel (nparts work-groups).
-// One work-group; writes out[0] nu_hot, out[1] nu_cold, out[2] max |u|, out[3] sum f',
-// out[4] non-finite flag.
+// ny wall nodes; part = the partial results of observe_kernel (nparts work-groups).
+// One work-group; writes out[0] nu_hot, out[1] nu_cold, then out[2 + k] the reduction of
+// partial result k: max |u|, sum f', non-finite flag, min T, max T, max |phi p - rho0 cs^2|.
 template <typename S, typename R, int L>
 __global__ __launch_bounds__(256) void nusselt_kernel(const S* __restrict__ src, Geo G,
                                                       Phys<R> P, double L_over_dT,
@@ -215,15 +241,20 @@ __global__ __launch_bounds__(256) void nusselt_kernel(const S* __restrict__ src,
         const double scale = -L_over_dT / double(G.ny - 1);
         out[0] = scale * sh;
         out[1] = scale * sc;
-        double a = 0.0, b = 0.0, f = 0.0;
-        for (int i = 0; i < nparts; ++i) {
-            a = fmax(a, part[3 * i + 0]);
-            b += part[3 * i + 1];
-            f = fmax(f, part[3 * i + 2]);
+        double r[kObsParts];
+#pragma unroll
+        for (int k = 0; k < kObsParts; ++k) r[k] = part[k];
+        for (int i = 1; i < nparts; ++i) {
+            const double* q = part + kObsParts * i;
+            r[0] = obs_max(r[0], q[0]);
+            r[1] += q[1];
+            r[2] = obs_max(r[2], q[2]);
+            r[3] = obs_min(r[3], q[3]);
+            r[4] = obs_max(r[4], q[4]);
+            r[5] = obs_max(r[5], q[5]);
         }
-        out[2] = a;
-        out[3] = b;
-        out[4] = f;
+#pragma unroll
+        for (int k = 0; k < kObsParts; ++k) out[2 + k] = r[k];
     }
 }
 

@@ -1,0 +1,70 @@
+"""Writes ``batch64_stability.txt``: which cavities of the batched workload stay finite over its
+10,000 steps, by the FP64 CPU oracle alone (``oracle/``), on the seeded draw of
+``paper_1308_2071_amd.workloads.batch64`` (seed 13082072).  Nothing here comes from the HIP
+path.
+
+    python tests/golden/make_batch64_stability.py [processes]
+
+Each cavity runs from rest for 10,000 steps; its observables (Eq. (38) Nusselt numbers, max |u|,
+min and max T and the oracle's divergence flag) are taken every 500 steps.  One line per
+cavity: its parameters, tau_v of Eq. (37b), the first sampled step at which the flag is set
+(-1: never) and the observables at step 10,000.  The cavities run in parallel processes, one
+oracle thread each.
+"""
+import os
+import sys
+import time
+from multiprocessing import Pool
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+from oracle import ref  # noqa: E402
+from paper_1308_2071_amd import workloads  # noqa: E402
+
+STEPS = 10000
+EVERY = 500
+OUT = os.path.join(HERE, "batch64_stability.txt")
+
+
+def run(i):
+    ref.set_threads(1)
+    c = workloads.batch64()[i]
+    lat = ref.RefLattice(phi_uniform=c["phi"], **c["params"])
+    first = -1
+    t0 = time.time()
+    o = None
+    for _ in range(STEPS // EVERY):
+        lat.step(EVERY)
+        o = lat.observables()
+        if first < 0 and o["diverged"]:
+            first = lat.time
+    tau_v = ref.derived(**c["params"])["tau_v"]
+    print(f"cavity {i}: first flag {first}, {time.time() - t0:.0f} s", flush=True)
+    return (i, c, tau_v, first, o)
+
+
+def main():
+    nproc = int(sys.argv[1]) if len(sys.argv) > 1 else 8
+    cav = workloads.batch64()
+    order = sorted(range(len(cav)), key=lambda i: -cav[i]["params"]["nx"])  # largest first
+    with Pool(nproc) as pool:
+        rows = sorted(pool.map(run, order, chunksize=1))
+    with open(OUT, "w") as f:
+        f.write("# FP64 CPU oracle on the batched workload (64 cavities, seed 13082072): every\n"
+                "# cavity from rest for 10000 steps, observables every 500 steps.  first_flag:\n"
+                "# first sampled step with the oracle's divergence flag set (-1: never).  The\n"
+                "# last five columns are the observables at step 10000.  Written by\n"
+                "# tests/golden/make_batch64_stability.py (oracle only).\n")
+        f.write("# i side Ra Pr Da phi tau_v first_flag nu_hot nu_cold max_speed T_min T_max\n")
+        for i, c, tau_v, first, o in rows:
+            p = c["params"]
+            f.write(f"{i} {p['nx']} {p['Ra']!r} {p['Pr']!r} {p['Da']!r} {c['phi']!r} "
+                    f"{tau_v!r} {first} {o['nu_hot']!r} {o['nu_cold']!r} {o['max_speed']!r} "
+                    f"{o['T_min']!r} {o['T_max']!r}\n")
+    print(OUT)
+
+
+if __name__ == "__main__":
+    main()

@@ -34,11 +34,29 @@ def test_every_declared_symbol_is_exported(lbm):
     assert set(names) == set(_abi.EXPORTED)
 
 
-def test_param_struct_layout_matches_header(lbm):
-    # the ctypes mirror must have the C layout: 8-byte aligned doubles after int32 pairs
+def test_param_struct_layout_matches_header(lbm, tmp_path):
+    """The ctypes mirrors have the layout the C compiler gives the header's structs: every
+    field's offset and the sizes, printed by a program compiled against include/lbm.h."""
+    import subprocess
     from paper_1308_2071_amd._abi import LbmObs, LbmParams
-    assert C.sizeof(LbmParams) == 8 + 16 + 32 + 4 * 8 + 4 * 8 + 5 * 8 + 8 + 8 + 16 + 3 * 8 + 2 * 8 + 8 + 8
-    assert C.sizeof(LbmObs) == 48
+    structs = {"lbm_params": LbmParams, "lbm_obs": LbmObs}
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "lbm.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        src.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            src.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    src.append("return 0; }")
+    (tmp_path / "layout.c").write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.check_call(["gcc", "-std=c11", "-I", inc, "-o", str(exe),
+                           str(tmp_path / "layout.c")])
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    got = {tuple(line.split()[:2]): int(line.split()[2]) for line in out.splitlines()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
 
 def test_defaults_are_the_papers(lbm):

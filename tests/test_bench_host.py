@@ -47,12 +47,18 @@ def test_roofline_object_of_a_fused_run(monkeypatch):
     nodes = 4096 * 4096
     ms = 0.25                                  # per step; a launch makes two
     run = {"ms": ms, "achieved": bench.BYTES_PER_NODE_FP32 * nodes / (ms * 1e-3) / 1e9,
-           "shape": (2, 0, 6, 11611), "kernel": bench.kernel_name("fp32", (2, 0, 6, 11611))}
+           "shape": (2, 0, 6, 11611), "kernel": bench.kernel_name("fp32", (2, 0, 6, 11611)),
+           "nodes": nodes}
     o = bench.roofline_obj(run)
     assert o["kernel"] == "tb2_step_kernel<float,float,true>" and o["steps_per_launch"] == 2
     assert abs(o["launch_ms"] - 0.5) < 1e-12 and o["rows_per_segment"] == 6
     assert abs(o["frac"] - run["achieved"] / 8000.0) < 1e-4 and o["bound"] == "hbm"
     assert o["traffic"] == 2_000_000_000 and abs(o["measured_hbm_GBps"] - 4000.0) < 0.1
+    # the launch's own minimum: 120 B per node once, over the launch (two updates)
+    assert o["own_min_bytes_per_launch"] == 120 * nodes
+    assert abs(o["frac_own_min"] - 120 * nodes / 0.5e-3 / 8e12) < 1e-4
+    assert abs(o["frac_measured_hbm"] - 0.5) < 1e-4
+    assert abs(o["traffic_vs_own_min"] - 2e9 / (120 * nodes)) < 1e-3
 
 
 def test_kernel_names():

@@ -12,6 +12,7 @@ import torch
 
 from oracle import ref
 from paper_1308_2071_amd import Batch, Cavity, workloads
+from pressure_gauge import phip_gauged
 
 pytestmark = pytest.mark.gpu
 
@@ -156,7 +157,50 @@ def test_batch64_workload_runs_and_matches_plain_on_sampled_cavities(tmp_path):
         for k in FIELDS:
             d = g[k].double().cpu().numpy() - o[k]
             if k == "p":
-                d = d - d.mean()     # the free pressure level
+                d = phip_gauged(d, float(np.float32(phis[i])))   # the free phi p level
             rng = max(o[k].max() - o[k].min(), 1e-2 * np.abs(o[k]).max())
             assert np.abs(d).max() <= 1e-4 * rng, (nx, k, np.abs(d).max() / rng)
         assert abs(obs[i]["nu_hot"] - o["nu_hot"]) <= 1e-3, (nx, obs[i]["nu_hot"], o["nu_hot"])
+
+
+def read_stability():
+    """The oracle's record of the batched workload over its 10,000 steps (written by
+    tests/golden/make_batch64_stability.py, oracle only)."""
+    rows = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "batch64_stability.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            v = line.split()
+            rows[int(v[0])] = dict(first_flag=int(v[7]), nu_hot=float(v[8]),
+                                   nu_cold=float(v[9]), max_speed=float(v[10]))
+    return rows
+
+
+def test_batch64_full_10k_steps_against_the_oracle_record(tmp_path):
+    """All 10,000 steps of the batched workload in FP32, in the graph-replayed form the
+    benchmark times: the cavities the library flags as diverged are exactly those the FP64
+    oracle flags (0 and 9, whose tau_v lies beyond the step's linear stability limit), and every
+    other cavity's Nusselt numbers are within 1e-3 of the oracle's and its max |u| within 1e-3
+    of it relative."""
+    rec = read_stability()
+    cav = workloads.batch64()
+    params = [dict(c["params"], dtype="fp32") for c in cav]
+    b = Batch(params, [c["phi"] for c in cav], tune_cache_path=str(tmp_path / "tune.txt"))
+    b.step(10000)
+    s, obs = b.observables()
+    flagged = sorted(i for i, o in enumerate(obs) if o["diverged"])
+    want = sorted(i for i, r in rec.items() if r["first_flag"] >= 0)
+    assert flagged == want == [0, 9]
+    assert s == -4
+    worst = 0.0
+    for i, o in enumerate(obs):
+        if i in want:
+            continue
+        r = rec[i]
+        e = max(abs(o["nu_hot"] - r["nu_hot"]), abs(o["nu_cold"] - r["nu_cold"]))
+        worst = max(worst, e)
+        assert e <= 1e-3, (i, o["nu_hot"], r["nu_hot"], o["nu_cold"], r["nu_cold"])
+        assert abs(o["max_speed"] - r["max_speed"]) <= 1e-3 * r["max_speed"], i
+    print(f"batch64 10k steps: flagged {flagged}, worst |dNu| of the rest {worst:.2e}")
+

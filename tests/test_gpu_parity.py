@@ -6,8 +6,10 @@ the 64 x 64 cavity; FP32 1e-4 of each field's range (range = max - min of the or
 and Nu within 1e-3; FP32 storage with FP64 arithmetic ("fp32_f64") 1e-5 and 1e-4.  p is the
 pressure of Eq. (23) less its rest value rho0 cs^2 / phi, as the library reports it (the
 oracle's p is converted in FP64).  FP32 compares p up to a constant: the density is fixed at
-rho0, only pressure differences enter the momentum equation and nothing pins the level, which
-rounding moves.  In the first steps a field's range can be far below its
+rho0, only pressure differences enter the momentum equation and nothing pins the level of phi p,
+which rounding moves (a uniform phi p shift is exact gauge of the step, pinned by
+``test_oracle_gauge.py``; with per-node phi it moves p by c / phi(x)).  In the first steps a
+field's range can be far below its
 magnitude; there the range is floored at 1e-2 of the field's magnitude, so the bar never drops
 below ~15 FP32 ulps of the value.  For FP32-storage runs the oracle receives the FP32-rounded
 phi and K, so only the arithmetic and the storage differ.
@@ -18,6 +20,7 @@ import torch
 
 from oracle import ref
 from paper_1308_2071_amd import Cavity, workloads
+from pressure_gauge import phip_gauged
 
 pytestmark = pytest.mark.gpu
 
@@ -46,6 +49,7 @@ def run_pair(params, steps, phi=None, K=None, phi_u=0.6, dtype="fp64", chunks=No
         lat.step(n)
         g = cav.observables()
         r = lat.observables(dynamic_pressure=True)
+        r["phi"] = phi if phi is not None else phi_u
         yield {k: (g[k].double().cpu().numpy() if k in FIELDS else g[k]) for k in g}, r
     cav.close()
 
@@ -60,9 +64,8 @@ def assert_match(g, r, dtype, atol64=1e-12, what="", floor=1e-2):
             rng = max(b.max() - b.min(), floor * np.abs(b).max(), 1e-12)
             d = a - b
             if k == "p":
-                # the pressure level is a free constant (density fixed at rho0; only pressure
-                # differences enter the momentum equation): FP32 is compared up to it
-                d = d - d.mean()
+                # the level of phi p is free: FP32 is compared up to a uniform phi p shift
+                d = phip_gauged(d, r["phi"])
             err = np.abs(d).max() / rng
             assert err <= RTOL[dtype][0], f"{what} {k}: {err:.3e} of range"
     tol = atol64 * 100 if dtype == "fp64" else RTOL[dtype][1]
@@ -186,6 +189,36 @@ def test_divergence_is_reported():
     cav.step(3)
     o = cav.observables(fields=False)
     assert o["diverged"] and o["status"] == -4
+
+
+def test_overflowing_velocity_is_reported():
+    """|v|^2 overflowing (FP64) makes Eq. (21)'s denominator infinite and u = 0 while T and p
+    stay finite; the |v| check reports it (LBM_DIV_NONFINITE).  The state is planted through
+    lbm_load: f'_1 at (8, 8) and f'_3 at (10, 8) of +-1e200 both stream into (9, 8)."""
+    params = dict(nx=16, ny=16, Ra=1e4, Pr=0.71, Da=1e-2, dtype="fp64")
+    cav = Cavity(params, phi_uniform=0.6)
+    snap = cav.save()
+    pitch, plane = 64, 64 * 16
+    st = snap[64:].view(np.float64)
+    st[1 * plane + 8 * pitch + 8] = 1e200
+    st[3 * plane + 8 * pitch + 10] = -1e200
+    cav.load(snap)
+    o = cav.observables(fields=False)
+    assert o["status"] == -4 and o["diverged"]
+    assert o["why"] & 1 and o["max_speed"] < 0.1 and np.isfinite(o["T_max"])
+    cav.close()
+
+
+def test_unstable_cavity_is_reported_in_fp64():
+    """Cavity 0 of the batched draw (512^2, tau_v 4.83, beyond the step's linear stability
+    limit of about 4.6455): the FP64 library reports LBM_E_DIVERGED by step 10,000, as the FP64
+    oracle does (before the |v| and bounds checks both returned OK on u = 0 and T ~ 1e217)."""
+    c = workloads.batch64()[0]
+    cav = Cavity(dict(c["params"], dtype="fp64"), phi_uniform=c["phi"])
+    cav.step(10000)
+    o = cav.observables(fields=False)
+    assert o["diverged"] and o["status"] == -4, o
+    cav.close()
 
 
 HEAT_CASES = {
