@@ -148,7 +148,7 @@ def cpu_model():
 def batch_stability(torch, params, phis, steps, every=500):
     """Untimed pass over the batched workload: observables of every cavity every `every` steps;
     for each cavity the library flags as diverged, the first sampled step and the reasons
-    (LBM_DIV_* bits: 1 non-finite, 2 |u| > cs, 4 T out of bounds, 8 phi p out of bounds)."""
+    (LBM_DIV_* bits: 1 non-finite, 2 |u| > cs, 4 T out of bounds)."""
     import tempfile
     from paper_1308_2071_amd import Batch
     first = {}

@@ -121,8 +121,6 @@ typedef struct {
                                /* side is isothermal (conduction alpha_e T'' = -Q from one    */
                                /* isothermal side), else |Q| n / sigma (Eq. (3) with no heat  */
                                /* leaving); alpha_e = sigma csT^2 (tau_T - 1/2), Eq. (A9)     */
-#define LBM_DIV_PRESSURE 8     /* phi p leaves (0, 2 rho0 cs^2): |phi p - rho0 cs^2| exceeds  */
-                               /* the rest value rho0 cs^2 (Eq. (23))                        */
 
 /* Observables at the current time level. */
 typedef struct {
@@ -135,7 +133,9 @@ typedef struct {
     int32_t why;      /* the LBM_DIV_* bits that hold (0 when not diverged)                    */
     double T_min;     /* min T over the lattice (Eq. (36))                                     */
     double T_max;     /* max T over the lattice                                                */
-    double phip_dev;  /* max |phi p - rho0 cs^2| over the lattice (Eq. (23))                   */
+    double phip_dev;  /* max |phi p - rho0 cs^2| over the lattice (Eq. (23)); the level of phi */
+                      /* p is a gauge of the step and drifts in long runs, so it is reported */
+                      /* but not part of the divergence flag                                 */
 } lbm_obs;
 
 typedef struct lbm_ctx lbm_ctx;

@@ -588,8 +588,9 @@ static void temperature_bounds(const ref_ctx *c, double out[2]) {
  *   - a field (u, p, T) or |v| of Eq. (22) is not finite (|v|^2 overflowing makes the
  *     denominator of Eq. (21) infinite and u = 0, so u alone cannot show it),
  *   - max |u| exceeds cs,
- *   - T leaves the interval of temperature_bounds, or
- *   - phi p leaves (0, 2 rho0 cs^2), i.e. |phi p - rho0 cs^2| exceeds its rest value. */
+ *   - T leaves the interval of temperature_bounds.
+ * (The level of phi p is a gauge of the step that drifts slowly in long runs; max
+ * |phi p - rho0 cs^2| is reported but not judged.) */
 void ref_observables(ref_ctx *c, double *ux, double *uy, double *pr, double *T, double *out) {
     stream(c);
     macros_and_walls(c);
@@ -641,10 +642,8 @@ void ref_observables(ref_ctx *c, double *ux, double *uy, double *pr, double *T, 
     out[3] = fabs(mass - mass_ref) / mass_ref;
     double tb[2];
     temperature_bounds(c, tb);
-    out[4] = (bad || !(umax <= sqrt(c->d.cs2)) || !(tmin >= tb[0]) || !(tmax <= tb[1]) ||
-              !(pdev <= prest))
-                 ? 1.0
-                 : 0.0;
+    out[4] = (bad || !(umax <= sqrt(c->d.cs2)) || !(tmin >= tb[0]) || !(tmax <= tb[1])) ? 1.0
+                                                                                        : 0.0;
     out[5] = tmin;
     out[6] = tmax;
     out[7] = pdev;

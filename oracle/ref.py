@@ -184,7 +184,7 @@ class RefLattice:
         ``dynamic_pressure`` p less its rest value rho0 cs^2 / phi (cs^2 = 1/3), node by node.
         Also max |u|, the mass deviation, min and max T, max |phi p - rho0 cs^2| and the
         divergence flag (non-finite u, p, T or |v|; |u| > cs; T outside the bounds of the
-        walls, T_init and the heat source widened by dT; phi p outside (0, 2 rho0 cs^2))."""
+        walls, T_init and the heat source widened by dT)."""
         shp = (self.ny, self.nx)
         ux, uy, p, T = (np.empty(shp) for _ in range(4))
         out = np.zeros(8)

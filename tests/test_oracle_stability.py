@@ -243,21 +243,33 @@ def test_heat_source_widens_the_temperature_bounds(oracle):
         assert o["diverged"] == flagged, (T_node, rise)
 
 
-def test_flag_catches_pressure_outside_its_range(oracle):
-    """phi p must stay in (0, 2 rho0 cs^2): a node whose post-streaming populations carry a
-    phi p shifted by 0.4 (> rho0 cs^2) is flagged, one shifted by 0.2 is not."""
+def test_pressure_level_is_reported_not_judged(oracle):
+    """The level of phi p is a gauge of the step (``test_oracle_gauge.py``) and drifts slowly in
+    long runs, even in FP64: a node whose phi p is shifted by 0.4 (more than the rest value
+    rho0 cs^2) is reported in phip_dev_max but not flagged."""
     w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
-    for shift, flagged in ((0.2, False), (0.4, True)):
-        lat = small_cavity()
-        f, g = lat.get_state()
-        # Eq. (13): a phi p shift c changes f_0 by -(1 - w0) c / cs^2 and f_i by w_i c / cs^2
-        for i in range(9):
-            dfi = -(1 - w[0]) * shift * 3 if i == 0 else w[i] * shift * 3
-            f[i, 7 - EY[i], 7 - EX[i]] += dfi
-        lat.set_state(f, g, 0)
-        o = lat.observables()
-        assert abs(o["phip_dev_max"] - shift) < 1e-12
-        assert o["diverged"] == flagged, shift
+    lat = small_cavity()
+    f, g = lat.get_state()
+    # Eq. (13): a phi p shift c changes f_0 by -(1 - w0) c / cs^2 and f_i by w_i c / cs^2
+    for i in range(9):
+        f[i, 7 - EY[i], 7 - EX[i]] += -(1 - w[0]) * 0.4 * 3 if i == 0 else w[i] * 0.4 * 3
+    lat.set_state(f, g, 0)
+    o = lat.observables()
+    assert abs(o["phip_dev_max"] - 0.4) < 1e-12
+    assert not o["diverged"]
+
+
+def test_pressure_level_drifts_in_a_long_fp64_run(oracle):
+    """The drift the previous test allows for: a 150^2 clear-fluid cavity (FP64 oracle) moves
+    its phi p level by more than 1e-4 between steps 10,000 and 20,000 and stays unflagged."""
+    lat = ref.RefLattice(phi_uniform=1.0, **workloads.cavity(150, Ra=1e5, Pr=0.7, Da=-1.0))
+    ref.set_threads(os.cpu_count() or 1)
+    lat.step(10000)
+    a = lat.observables()
+    lat.step(10000)
+    b = lat.observables()
+    assert b["phip_dev_max"] - a["phip_dev_max"] > 1e-4
+    assert not b["diverged"]
 
 
 @pytest.mark.slow
