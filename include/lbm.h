@@ -251,6 +251,27 @@ lbm_status lbm_batch_fields(lbm_ctx* c, int32_t i, void* ux, void* uy, void* p, 
  * its work-groups per launch, out[7] its strips (wavefronts) per work-group. */
 lbm_status lbm_batch_shape(const lbm_ctx* c, int32_t* out);
 
+/* ---------------------------------------------------------------------------------------- */
+/* For callers that cannot allocate device memory (tight serving loops, harnesses that       */
+/* forbid hipMalloc): one cavity run from rest without a workspace.                          */
+/* ---------------------------------------------------------------------------------------- */
+
+/* The results of lbm_init(p, phi, K, phi_uniform) + lbm_step(nsteps) + lbm_observables(o, ux,
+ * uy, pr, T) on the same stream, bitwise (the same kernels in the same order), with the cavity
+ * kept in a device array of the library instead of a caller's workspace: nothing is allocated,
+ * on the device or the host.  Arguments are those of the three calls; phi, K (optional) and
+ * ux, uy, pr, T (optional) are device arrays [ny][nx] of p->dtype, o is host memory.  The
+ * array holds 64 MiB per GPU (kept from the library's first use on a GPU until the process
+ * ends): a cavity whose workspace (lbm_workspace_size) exceeds it gives LBM_E_NOMEM before any
+ * device work, e.g. FP32 cavities up to about 700 x 700 fit.  No tape (checkpoint_every must
+ * be 0: LBM_E_UNSUPPORTED).  Every call on a GPU uses that GPU's one array, so calls that
+ * overlap on one GPU (other host threads, or other streams before this call returns) race;
+ * the call synchronises the stream before returning, so calls in sequence do not.  Errors as
+ * lbm_init and lbm_observables (LBM_E_DIVERGED when the run diverged). */
+lbm_status lbm_run_noalloc(const lbm_params* p, const void* phi, const void* K,
+                           double phi_uniform, int64_t nsteps, lbm_obs* o, void* ux, void* uy,
+                           void* pr, void* T, void* hip_stream);
+
 /* Human-readable name of a status code. */
 const char* lbm_status_string(lbm_status s);
 

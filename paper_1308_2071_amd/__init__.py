@@ -27,7 +27,7 @@ __all__ = [
     "lbm_observables", "lbm_grad", "lbm_stream_function", "lbm_state_size", "lbm_save", "lbm_load", "lbm_destroy",
     "lbm_batch_workspace_size", "lbm_batch_init", "lbm_batch_step", "lbm_batch_observables",
     "lbm_batch_fields", "lbm_batch_shape", "lbm_step_shape", "lbm_status_string",
-    "lbm_last_error", "Cavity", "Batch", "NuHot",
+    "lbm_last_error", "lbm_run_noalloc", "Cavity", "Batch", "NuHot",
 ]
 
 _ARRAY_FIELDS = ("bc", "T_wall", "ext_accel")
@@ -158,6 +158,22 @@ def lbm_step_shape(ctx: int):
     out = (C.c_int32 * 4)()
     check(library().lbm_step_shape(ctx, out), "lbm_step_shape")
     return tuple(out)
+
+
+def lbm_run_noalloc(p: LbmParams, phi, K, phi_uniform: float, nsteps: int, ux=None, uy=None,
+                    pr=None, T=None, stream=None):
+    """One cavity run from rest for nsteps steps in the library's own device array (no
+    workspace, nothing allocated); returns (status, LbmObs) like lbm_observables."""
+    o = LbmObs()
+    if stream is None:
+        dev = next((t.device for t in (phi, K, ux, uy, pr, T) if t is not None), None)
+        stream = _abi.current_stream_handle(dev)
+    s = library().lbm_run_noalloc(C.byref(p), ptr(phi), ptr(K), float(phi_uniform),
+                                  int(nsteps), C.byref(o), ptr(ux), ptr(uy), ptr(pr), ptr(T),
+                                  stream)
+    if s not in (_abi.LBM_OK, _abi.LBM_E_DIVERGED):
+        check(s, "lbm_run_noalloc")
+    return s, o
 
 
 def lbm_status_string(s: int) -> str:

@@ -89,6 +89,7 @@ def library() -> C.CDLL:
         "lbm_batch_fields": [vp, i32, vp, vp, vp, vp],
         "lbm_batch_shape": [vp, C.POINTER(i32)],
         "lbm_step_shape": [vp, C.POINTER(i32)],
+        "lbm_run_noalloc": [P, vp, vp, dbl, i64, C.POINTER(LbmObs), vp, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -107,7 +108,7 @@ EXPORTED = (
     "lbm_observables", "lbm_grad", "lbm_stream_function", "lbm_state_size", "lbm_save", "lbm_load", "lbm_destroy",
     "lbm_batch_workspace_size", "lbm_batch_init", "lbm_batch_step", "lbm_batch_observables",
     "lbm_batch_fields", "lbm_batch_shape", "lbm_step_shape", "lbm_status_string",
-    "lbm_last_error",
+    "lbm_last_error", "lbm_run_noalloc",
 )
 
 

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -936,6 +937,37 @@ lbm_status observe_ctx(lbm_ctx* c, lbm_obs* o, void* ux, void* uy, void* p, void
     return LBM_OK;
 }
 
+// ---- device memory for lbm_run_noalloc --------------------------------------------------------
+// The one entry point that allocates nothing keeps its cavity (two state buffers, the medium
+// planes and the observables' partial results) in this array.  Each GPU the library runs on
+// holds its own copy, at its own address, from the module's load until the process ends.  In
+// host code the array's name is only a stand-in for the symbol: device addresses come from
+// hipGetSymbolAddress, per device.
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+// The current device's address of `scratch`, looked up once per device with that device
+// current and kept.
+lbm_status scratch_address(void** out) {
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(LBM_E_UNSUPPORTED, "device %d beyond the %d the library tracks", dev,
+                    kMaxDevices);
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(LBM_E_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        addr[dev] = ptr;
+    }
+    *out = addr[dev];
+    return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1466,6 +1498,45 @@ lbm_status lbm_batch_shape(const lbm_ctx* c, int32_t* out) {
     out[6] = c->b_tb_nwg;
     out[7] = c->b_tb_rows > 0 ? c->b_tb_waves : 0;
     return LBM_OK;
+}
+
+lbm_status lbm_run_noalloc(const lbm_params* p, const void* phi, const void* K,
+                           double phi_uniform, int64_t nsteps, lbm_obs* o, void* ux, void* uy,
+                           void* pr, void* T, void* hip_stream) {
+    if (!p || !o) return fail(LBM_E_INVAL, "null argument");
+    lbm_status s = validate(*p);
+    if (s != LBM_OK) return s;
+    if (p->checkpoint_every != 0)
+        return fail(LBM_E_UNSUPPORTED, "lbm_run_noalloc keeps no adjoint tape");
+    if (nsteps < 0) return fail(LBM_E_INVAL, "nsteps < 0");
+    if (!phi && !(phi_uniform > 0 && phi_uniform <= 1))
+        return fail(LBM_E_INVAL, "phi_uniform = %g outside (0, 1]", phi_uniform);
+    const Layout L = make_layout(*p, 1, phi != nullptr || K != nullptr);
+    if (L.total > kNoAllocBytes)
+        return fail(LBM_E_NOMEM,
+                    "a %d x %d cavity needs %zu bytes of device memory; lbm_run_noalloc holds "
+                    "at most %zu",
+                    p->nx, p->ny, L.total, kNoAllocBytes);
+    void* ws = nullptr;
+    s = scratch_address(&ws);
+    if (s != LBM_OK) return s;
+    lbm_ctx c;  // on the stack: no host allocation either
+    s = setup_ctx(&c, *p, L, 0, phi, K, phi_uniform, ws, hip_stream);
+    if (s != LBM_OK) return s;
+    int64_t left = nsteps;
+    if (fused(&c)) {
+        for (; left >= 2; left -= 2) {
+            HIP_TRY(advance2(&c, c.cur, c.stream), "step launch");
+            c.cur = 1 - c.cur;
+            c.step += 2;
+        }
+    }
+    for (; left > 0; --left) {
+        HIP_TRY(advance(&c, c.cur, c.stream), "step launch");
+        c.cur = 1 - c.cur;
+        c.step += 1;
+    }
+    return observe_ctx(&c, o, ux, uy, pr, T);
 }
 
 }  // extern "C"
