@@ -60,9 +60,10 @@ def main():
         f.write("# i side Ra Pr Da phi tau_v first_flag nu_hot nu_cold max_speed T_min T_max\n")
         for i, c, tau_v, first, o in rows:
             p = c["params"]
-            f.write(f"{i} {p['nx']} {p['Ra']!r} {p['Pr']!r} {p['Da']!r} {c['phi']!r} "
-                    f"{tau_v!r} {first} {o['nu_hot']!r} {o['nu_cold']!r} {o['max_speed']!r} "
-                    f"{o['T_min']!r} {o['T_max']!r}\n")
+            vals = [p["Ra"], p["Pr"], p["Da"], c["phi"], tau_v]
+            obs = [o[k] for k in ("nu_hot", "nu_cold", "max_speed", "T_min", "T_max")]
+            f.write(f"{i} {p['nx']} " + " ".join(repr(float(v)) for v in vals) + f" {first} "
+                    + " ".join(repr(float(v)) for v in obs) + "\n")
     print(OUT)
 
 
