@@ -114,24 +114,12 @@ __device__ __forceinline__ void macros_vjp(const R f[9], const R g[5], R phi, R 
                                            const Med<R>& md, const Phys<R>& P,
                                            const MacAdj<R>& A0, R af[9], R ag[5], R& lphi,
                                            R& lK) {
-    // forward recompute
-    const R theta = ((g[0] + g[1]) + (g[2] + g[3]) + g[4]) + P.hQs;
-    const R Gx = P.ax, Gy = P.ay + P.gbeta * theta;
-    const R jx = (f[1] - f[3]) + (f[5] - f[6]) - (f[7] - f[8]);
-    const R jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
-    const R hphi = R(0.5) * phi;
-    const R vx = jx * P.inv_rho0 + hphi * Gx;
-    const R vy = jy * P.inv_rho0 + hphi * Gy;
-    const R l0 = R(0.5) + R(0.25) * md.c_lin;
-    const R l1 = R(0.5) * md.c_nl;
-    const R vm = sqrt(vx * vx + vy * vy);
-    const R q = sqrt(l0 * l0 + l1 * vm);
-    const R den = l0 + q;
-    const R inv_den = R(1) / den;
-    const R ux = vx / den, uy = vy / den;     // as the forward step computes them
-    const R uu = ux * ux + uy * uy;
-    const R um = sqrt(uu);
-    const R drag = md.c_lin + md.c_nl * um;
+    // forward recompute, exactly as the forward step computes it
+    const Vel<R> v = velocity<R>(f, g, md, P);
+    const R Gx = v.Gx, Gy = v.Gy, hphi = R(0.5) * phi;
+    const R vx = v.vx, vy = v.vy, l0 = v.l0, l1 = v.l1, vm = v.vm, q = v.q;
+    const R inv_den = R(1) / v.den;
+    const R ux = v.ux, uy = v.uy, uu = v.uu, um = v.um, drag = v.drag;
     // reverse
     R lux = A0.ux, luy = A0.uy, lth = A0.theta, lip = A0.ip;
     R lGx = phi * A0.Fx, lGy = phi * A0.Fy;

@@ -88,17 +88,29 @@ struct Mac {
     R theta, ux, uy, P, Fx, Fy, vv;
 };
 
-__device__ __forceinline__ float rsq(float x) { return __frsqrt_rn(x); }
-__device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+// Arithmetic forms.  The build does not contract a * b + c on its own (-ffp-contract=off), so
+// that every kernel computing a node rounds exactly alike; where a fused multiply-add is
+// wanted it is written out (fma), the same in every kernel.  Products by 2, 4, 0.25 and 0.5
+// are exact, so fma(2, a, b) rounds like 2 * a + b did.
+//
+// rsq_1ulp, sqrt_1ulp: in FP32 the hardware reciprocal square root and square root (within
+// 1 ulp) instead of the correctly rounded sequences (~15 instructions each).  They are used
+// only where one rounding more cannot act as a common gain: the medium coefficients of a
+// per-node medium (Eq. (5), different at every node), |v| inside Eq. (21)'s root (a small
+// correction to l0^2) and |u| in Eq. (4)'s Forchheimer term.  FP64 keeps sqrt.
+__device__ __forceinline__ float rsq_1ulp(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsq_1ulp(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float sqrt_1ulp(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double sqrt_1ulp(double x) { return sqrt(x); }
 
 template <typename R>
 __device__ __forceinline__ Med<R> medium_from(R phi, R K, const Phys<R>& P) {
     Med<R> m;
-    const R rK = rsq(K);
+    const R rK = rsq_1ulp(K);
     m.phi = phi;
     m.inv_phi = R(1) / phi;
     m.c_lin = phi * P.nu * (rK * rK);
-    m.c_nl = P.forch ? R(kErgun) * rsq(phi) * rK : R(0);
+    m.c_nl = P.forch ? R(kErgun) * rsq_1ulp(phi) * rK : R(0);
     return m;
 }
 
@@ -173,39 +185,59 @@ __device__ __forceinline__ void pull(const S* __restrict__ src, const Geo& G, in
     g[4] = R(at(plane(src, O ? 11 : 13, P), cn));
 }
 
+// The velocity part of the macroscopic recovery at a fluid node, shared by fluid_macros and
+// the adjoint's recompute so that both see the same values: theta = T - T0 (Eq. (36)), G
+// (Eq. (4)), v (Eq. (22)), l0, l1, |v|, the root q and den = l0 + q of Eq. (21), u = v / den,
+// |u|^2, |u| and the drag coefficient of Eq. (4).
+template <typename R>
+struct Vel {
+    R theta, Gx, Gy, vx, vy, l0, l1, vv, vm, q, den, ux, uy, uu, um, drag;
+};
+
+template <typename R>
+__device__ __forceinline__ Vel<R> velocity(const R f[9], const R g[5], const Med<R>& md,
+                                           const Phys<R>& P) {
+    Vel<R> v;
+    v.theta = ((g[0] + g[1]) + (g[2] + g[3]) + g[4]) + P.hQs;
+    v.Gx = P.ax;
+    v.Gy = fma(P.gbeta, v.theta, P.ay);
+    const R jx = (f[1] - f[3]) + (f[5] - f[6]) - (f[7] - f[8]);
+    const R jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    const R hphi = R(0.5) * md.phi;
+    v.vx = fma(hphi, v.Gx, jx * P.inv_rho0);
+    v.vy = fma(hphi, v.Gy, jy * P.inv_rho0);
+    v.l0 = fma(R(0.25), md.c_lin, R(0.5));
+    v.l1 = R(0.5) * md.c_nl;
+    v.vv = fma(v.vx, v.vx, v.vy * v.vy);
+    v.vm = sqrt_1ulp(v.vv);
+    v.q = sqrt(fma(v.l0, v.l0, v.l1 * v.vm));
+    v.den = v.l0 + v.q;
+    // divide rather than multiply by a rounded reciprocal: in a uniform medium the denominator
+    // is nearly the same at every node, so the reciprocal's rounding would act as one common
+    // gain on the momentum, step after step
+    v.ux = v.vx / v.den;
+    v.uy = v.vy / v.den;
+    v.uu = fma(v.ux, v.ux, v.uy * v.uy);
+    v.um = sqrt_1ulp(v.uu);
+    v.drag = fma(md.c_nl, v.um, md.c_lin);
+    return v;
+}
+
 // Eqs. (36), (22), (21), (23), (4) at a fluid node, on deviation populations.
 template <typename R>
 __device__ __forceinline__ Mac<R> fluid_macros(const R f[9], const R g[5], const Med<R>& md,
                                                const Phys<R>& P) {
+    const Vel<R> v = velocity<R>(f, g, md, P);
     Mac<R> m;
-    const R theta = ((g[0] + g[1]) + (g[2] + g[3]) + g[4]) + P.hQs;
-    const R Gx = P.ax;
-    const R Gy = P.ay + P.gbeta * theta;
-    const R jx = (f[1] - f[3]) + (f[5] - f[6]) - (f[7] - f[8]);
-    const R jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
-    const R hphi = R(0.5) * md.phi;
-    const R vx = jx * P.inv_rho0 + hphi * Gx;
-    const R vy = jy * P.inv_rho0 + hphi * Gy;
-    const R l0 = R(0.5) + R(0.25) * md.c_lin;
-    const R l1 = R(0.5) * md.c_nl;
-    const R vv = vx * vx + vy * vy;
-    const R vmag = sqrt(vv);
-    // divide rather than multiply by a rounded reciprocal: in a uniform medium the denominator
-    // is nearly the same at every node, so the reciprocal's rounding would act as one common
-    // gain on the momentum, step after step
-    const R den = l0 + sqrt(l0 * l0 + l1 * vmag);
-    const R ux = vx / den, uy = vy / den;
-    const R uu = ux * ux + uy * uy;
     const R sum18 = ((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8]));
     // phi p = cs^2/(1 - w0) [sum_{i>=1} f_i + rho0 s0(u)], s0 = -w0 |u|^2 / (2 phi cs^2)
-    m.P = R(0.6) * (sum18 - R(2.0 / 3.0) * P.rho0 * uu * md.inv_phi);
-    const R drag = md.c_lin + md.c_nl * sqrt(uu);
-    m.theta = theta;
-    m.ux = ux;
-    m.uy = uy;
-    m.Fx = md.phi * Gx - drag * ux;
-    m.Fy = md.phi * Gy - drag * uy;
-    m.vv = vv;
+    m.P = R(0.6) * fma(R(-2.0 / 3.0) * P.rho0, v.uu * md.inv_phi, sum18);
+    m.theta = v.theta;
+    m.ux = v.ux;
+    m.uy = v.uy;
+    m.Fx = fma(-v.drag, v.ux, md.phi * v.Gx);
+    m.Fy = fma(-v.drag, v.uy, md.phi * v.Gy);
+    m.vv = v.vv;
     return m;
 }
 
@@ -263,70 +295,80 @@ __device__ __forceinline__ void collide(R f[9], R g[5], const Mac<R>& m, const M
                                         const Phys<R>& P) {
     // m' = M f' (rows of Eq. (11)); m0', m3', m5' are not needed: s0 = s3 = s5 = 1
     const R s14 = (f[1] + f[2]) + (f[3] + f[4]);
-    const R s58 = (f[5] + f[6]) + (f[7] + f[8]);
-    const R qx = (f[5] - f[6]) - (f[7] - f[8]);
-    const R qy = (f[5] + f[6]) - (f[7] + f[8]);
-    const R m1 = R(2) * s58 - s14 - R(4) * f[0];
-    const R m2 = s58 - R(2) * s14 + R(4) * f[0];
-    const R m4 = qx - R(2) * (f[1] - f[3]);
-    const R m6 = qy - R(2) * (f[2] - f[4]);
+    const R p56 = f[5] + f[6], p78 = f[7] + f[8];
+    const R d56 = f[5] - f[6], d78 = f[7] - f[8];
+    const R s58 = p56 + p78;
+    const R qx = d56 - d78;
+    const R qy = p56 - p78;
+    const R m1 = fma(R(-4), f[0], fma(R(2), s58, -s14));
+    const R m2 = fma(R(4), f[0], fma(R(-2), s14, s58));
+    const R m4 = fma(R(-2), f[1] - f[3], qx);
+    const R m6 = fma(R(-2), f[2] - f[4], qy);
     const R m7 = (f[1] - f[2]) + (f[3] - f[4]);
-    const R m8 = (f[5] - f[6]) + (f[7] - f[8]);
+    const R m8 = d56 + d78;
     // equilibrium moments (Eq. (16) less the rest state) and forcing (Eq. (19))
     const R r0 = P.rho0, ux = m.ux, uy = m.uy;
     const R rip = r0 * md.inv_phi;
-    const R uu = ux * ux + uy * uy;
-    const R e_eq = R(6) * m.P + R(3) * rip * uu;
-    const R eps_eq = R(-9) * m.P - R(3) * rip * uu;
-    const R pxx_eq = rip * (ux * ux - uy * uy);
+    const R uu = fma(ux, ux, uy * uy);
+    const R ruu = R(3) * rip * uu;
+    const R e_eq = fma(R(6), m.P, ruu);
+    const R eps_eq = fma(R(-9), m.P, -ruu);
+    const R pxx_eq = rip * fma(ux, ux, -(uy * uy));
     const R pxy_eq = rip * ux * uy;
-    const R S1 = R(6) * rip * (ux * m.Fx + uy * m.Fy);
-    const R S7 = R(2) * rip * (ux * m.Fx - uy * m.Fy);
-    const R S8 = rip * (ux * m.Fy + uy * m.Fx);
+    const R S1 = R(6) * rip * fma(ux, m.Fx, uy * m.Fy);
+    const R S7 = R(2) * rip * fma(ux, m.Fx, -(uy * m.Fy));
+    const R S8 = rip * fma(ux, m.Fy, uy * m.Fx);
     const R rFx = r0 * m.Fx, rFy = r0 * m.Fy;
-    // relaxation, then division by |row|^2 for M^-1 = M^T diag(1/|row|^2); the divisions by
-    // 36, 6 and 12 are correctly rounded (not products with the rounded reciprocal, whose
-    // error is one common gain on energy and momentum that accumulates step after step)
-    const R a1 = div_const(m1 - P.s_e * (m1 - e_eq) + P.os_e * S1, R(36), R(1.0 / 36.0));
-    const R a2 = div_const(m2 - P.s_eps * (m2 - eps_eq) - P.os_eps * S1, R(36), R(1.0 / 36.0));
-    const R a3 = div_const(r0 * ux + R(0.5) * rFx, R(6), R(1.0 / 6.0));
-    const R a4 = div_const(m4 - P.s_q * (m4 + r0 * ux) - P.os_q * rFx, R(12), R(1.0 / 12.0));
-    const R a5 = div_const(r0 * uy + R(0.5) * rFy, R(6), R(1.0 / 6.0));
-    const R a6 = div_const(m6 - P.s_q * (m6 + r0 * uy) - P.os_q * rFy, R(12), R(1.0 / 12.0));
-    const R a7 = (m7 - P.s_v * (m7 - pxx_eq) + P.os_v * S7) * R(0.25);
-    const R a8 = (m8 - P.s_v * (m8 - pxy_eq) + P.os_v * S8) * R(0.25);
+    // relaxation m - s (m - m_eq) + (1 - s/2) S, then division by |row|^2 for
+    // M^-1 = M^T diag(1/|row|^2); the divisions by 36, 6 and 12 are correctly rounded (not
+    // products with the rounded reciprocal, whose error is one common gain on energy and
+    // momentum that accumulates step after step)
+    const R a1 = div_const(fma(P.os_e, S1, fma(-P.s_e, m1 - e_eq, m1)), R(36), R(1.0 / 36.0));
+    const R a2 =
+        div_const(fma(-P.os_eps, S1, fma(-P.s_eps, m2 - eps_eq, m2)), R(36), R(1.0 / 36.0));
+    const R a3 = div_const(fma(R(0.5), rFx, r0 * ux), R(6), R(1.0 / 6.0));
+    const R a4 = div_const(fma(-P.os_q, rFx, fma(-P.s_q, fma(r0, ux, m4), m4)), R(12),
+                           R(1.0 / 12.0));
+    const R a5 = div_const(fma(R(0.5), rFy, r0 * uy), R(6), R(1.0 / 6.0));
+    const R a6 = div_const(fma(-P.os_q, rFy, fma(-P.s_q, fma(r0, uy, m6), m6)), R(12),
+                           R(1.0 / 12.0));
+    const R a7 = fma(P.os_v, S7, fma(-P.s_v, m7 - pxx_eq, m7)) * R(0.25);
+    const R a8 = fma(P.os_v, S8, fma(-P.s_v, m8 - pxy_eq, m8)) * R(0.25);
     // f' = M^T a (columns of Eq. (11)); a0 = 0 because the post-collision m0' is 0
-    const R c14 = -a1 - R(2) * a2;
-    const R c58 = R(2) * a1 + a2;
+    const R c14 = fma(R(-2), a2, -a1);
+    const R c58 = fma(R(2), a1, a2);
     f[0] = R(4) * (a2 - a1);
-    f[1] = c14 + (a3 - R(2) * a4) + a7;
-    f[2] = c14 + (a5 - R(2) * a6) - a7;
-    f[3] = c14 - (a3 - R(2) * a4) + a7;
-    f[4] = c14 - (a5 - R(2) * a6) - a7;
+    const R x4 = fma(R(-2), a4, a3), y6 = fma(R(-2), a6, a5);
+    f[1] = (c14 + x4) + a7;
+    f[2] = (c14 + y6) - a7;
+    f[3] = (c14 - x4) + a7;
+    f[4] = (c14 - y6) - a7;
     const R px = a3 + a4, py = a5 + a6;
-    f[5] = c58 + px + py + a8;
-    f[6] = c58 - px + py - a8;
-    f[7] = c58 - px - py + a8;
-    f[8] = c58 + px - py - a8;
+    f[5] = ((c58 + px) + py) + a8;
+    f[6] = ((c58 - px) + py) - a8;
+    f[7] = ((c58 - px) - py) + a8;
+    f[8] = ((c58 + px) - py) - a8;
 
     // thermal: n' = N g' (rows of Eq. (28)); with zeta0 = 1, n0'+ = theta + Q'''/(2 sigma)
     // (the source term of Eq. (34) with Psi0 = Q'''/sigma, Eq. (30))
-    const R T = P.T0 + m.theta;
+    const R Ts = (P.T0 + m.theta) * P.inv_sigma;
     const R n1 = g[1] - g[3];
     const R n2 = g[2] - g[4];
-    const R n3 = (g[1] + g[2]) + (g[3] + g[4]) - R(4) * g[0];
+    const R n3 = fma(R(-4), g[0], (g[1] + g[2]) + (g[3] + g[4]));
     const R n4 = (g[1] - g[2]) + (g[3] - g[4]);
     const R b0 = div_const(m.theta + P.hQs, R(5), R(1.0 / 5.0));
-    const R b1 = (n1 - P.z_T * (n1 - ux * T * P.inv_sigma)) * R(0.5);
-    const R b2 = (n2 - P.z_T * (n2 - uy * T * P.inv_sigma)) * R(0.5);
-    const R b3 = div_const(n3 - P.z3 * (n3 - P.varpi * m.theta) + P.psi3, R(20), R(1.0 / 20.0));
-    const R b4 = (n4 - P.z4 * n4) * R(0.25);
+    const R b1 = fma(-P.z_T, fma(-ux, Ts, n1), n1) * R(0.5);
+    const R b2 = fma(-P.z_T, fma(-uy, Ts, n2), n2) * R(0.5);
+    const R b3 = div_const(fma(-P.z3, fma(-P.varpi, m.theta, n3), n3) + P.psi3, R(20),
+                           R(1.0 / 20.0));
+    const R b4 = fma(-P.z4, n4, n4) * R(0.25);
     // g' = N^T b (columns of Eq. (28))
-    g[0] = b0 - R(4) * b3;
-    g[1] = (b0 + b3) + (b1 + b4);
-    g[2] = (b0 + b3) + (b2 - b4);
-    g[3] = (b0 + b3) - (b1 - b4);
-    g[4] = (b0 + b3) - (b2 + b4);
+    const R b03 = b0 + b3;
+    g[0] = fma(R(-4), b3, b0);
+    g[1] = b03 + (b1 + b4);
+    g[2] = b03 + (b2 - b4);
+    g[3] = b03 - (b1 - b4);
+    g[4] = b03 - (b2 + b4);
 }
 
 // Wall temperature rule: an isothermal side fixes T; at a corner of two isothermal sides the

@@ -164,15 +164,17 @@ __device__ __forceinline__ int tb_row(const Geo& G, int r) {
 }
 
 // One wavefront's share of a two-step launch: strip `strip` of row segment `seg` (rows per
-// segment `rows`).  Every wavefront of the work-group calls this with the same segment and
-// runs the same rows (an inactive one, past the last strip, stores nothing), since each row
-// ends with a work-group barrier.
-template <typename S, typename R, bool PN>
-__device__ __forceinline__ void tb2_segment(const S* __restrict__ src, S* __restrict__ dst,
-                                            const S* __restrict__ med, const Geo& G,
-                                            const Phys<R>& P, int strip, bool active, int seg,
-                                            int rows) {
+// segment `rows`), swept towards increasing y (REV false) or decreasing y (REV true).  Every
+// wavefront of the work-group calls this with the same segment and runs the same rows (an
+// inactive one, past the last strip, stores nothing), since each row ends with a work-group
+// barrier.
+template <typename S, typename R, bool PN, bool REV>
+__device__ __forceinline__ void tb2_sweep(const S* __restrict__ src, S* __restrict__ dst,
+                                          const S* __restrict__ med, const Geo& G,
+                                          const Phys<R>& P, int strip, bool active, int seg,
+                                          int rows) {
     constexpr unsigned B = sizeof(S);
+    constexpr int D = REV ? -1 : 1;              // direction of the sweep along y
     const unsigned PB = unsigned(G.plane) * B;   // bytes per plane
     const unsigned RB = unsigned(G.pitch) * B;   // bytes per row
     const __amdgpu_buffer_rsrc_t rs = buf_rsrc(src, 14 * PB);
@@ -198,20 +200,24 @@ __device__ __forceinline__ void tb2_segment(const S* __restrict__ src, S* __rest
     }
     // lanes 1..kTbCols write step n+2 at their column
     const bool out_lane = active && lane >= 1 && lane <= kTbCols && x0 - 1 + lane < G.nx;
-    const int y0 = seg * rows;
-    const int y1 = min(y0 + rows, G.ny);
-    S a[14], b[14], c[14];  // step n+1 at rows y-1, y, y+1 of this lane's column
-    Med<R> mdb, mdc;        // medium at (x, y) and (x, y + 1)
+    const int ylo = seg * rows;
+    const int yhi = min(ylo + rows, G.ny);
+    // the sweep runs y = yb, yb + D, ..., ye - D
+    const int yb = REV ? yhi - 1 : ylo;
+    const int ye = REV ? ylo - 1 : yhi;
+    // step n+1 at rows y - D (behind the sweep), y and y + D (ahead) of this lane's column
+    S bh[14], cur[14], ah[14];
+    Med<R> mdb, mdn;        // medium at (x, y) and (x, y + D)
     TbRaw<S> raw;
     {
         Med<R> unused;
-        int r = tb_row(G, y0 - 1);
+        int r = tb_row(G, yb - D);
         tb_load<S, PN>(rs, rm, G, PB, RB, cols, r, raw);
-        tb_finish<S, R, PN>(raw, G, P, x, r, a, unused);
-        r = tb_row(G, y0);
+        tb_finish<S, R, PN>(raw, G, P, x, r, bh, unused);
+        r = tb_row(G, yb);
         tb_load<S, PN>(rs, rm, G, PB, RB, cols, r, raw);
-        tb_finish<S, R, PN>(raw, G, P, x, r, b, mdb);
-        tb_load<S, PN>(rs, rm, G, PB, RB, cols, tb_row(G, y0 + 1), raw);
+        tb_finish<S, R, PN>(raw, G, P, x, r, cur, mdb);
+        tb_load<S, PN>(rs, rm, G, PB, RB, cols, tb_row(G, yb + D), raw);
         // 14 stores that the hardware drops, so that on entering the row loop, as on every
         // later row, the loads in flight are followed by 14 stores: the compiler's wait for
         // those loads at the top of the loop then leaves the previous row's stores in flight
@@ -219,17 +225,20 @@ __device__ __forceinline__ void tb2_segment(const S* __restrict__ src, S* __rest
 #pragma unroll
         for (int i = 0; i < 14; ++i) buf_store<S>(S(0), rd, kBufOutOfRange, i * PB);
     }
-    // y0 < y1 on every segment; the work-group's waves run the same rows
-    int y = y0;
+    // yb != ye on every segment; the work-group's waves run the same rows
+    int y = yb;
     do {
-        tb_finish<S, R, PN>(raw, G, P, x, tb_row(G, y + 1), c, mdc);
+        tb_finish<S, R, PN>(raw, G, P, x, tb_row(G, y + D), ah, mdn);
         // issue the next row's loads now; they complete during this row's work
-        tb_load<S, PN>(rs, rm, G, PB, RB, cols, tb_row(G, y + 2), raw);
+        tb_load<S, PN>(rs, rm, G, PB, RB, cols, tb_row(G, y + 2 * D), raw);
+        // step n+1 at rows y - 1 and y + 1, whichever way the sweep runs
+        const S* dn = REV ? ah : bh;   // row y - 1
+        const S* up = REV ? bh : ah;   // row y + 1
         // gather step n+1 populations arriving at (x, y): f_i from (x - ex_i, y - ey_i)
-        const S f1 = __shfl_up(b[1], 1, 64), g1 = __shfl_up(b[10], 1, 64);
-        const S f5 = __shfl_up(a[5], 1, 64), f8 = __shfl_up(c[8], 1, 64);
-        const S f3 = __shfl_down(b[3], 1, 64), g3 = __shfl_down(b[12], 1, 64);
-        const S f6 = __shfl_down(a[6], 1, 64), f7 = __shfl_down(c[7], 1, 64);
+        const S f1 = __shfl_up(cur[1], 1, 64), g1 = __shfl_up(cur[10], 1, 64);
+        const S f5 = __shfl_up(dn[5], 1, 64), f8 = __shfl_up(up[8], 1, 64);
+        const S f3 = __shfl_down(cur[3], 1, 64), g3 = __shfl_down(cur[12], 1, 64);
+        const S f6 = __shfl_down(dn[6], 1, 64), f7 = __shfl_down(up[7], 1, 64);
         const bool wall = (G.wallW && x == 0) || (G.wallE && x == G.nx - 1) ||
                           (G.wallS && y == 0) || (G.wallN && y == G.ny - 1);
         // Step n+2 runs on every lane; lanes that own no output (the strip's two halo lanes,
@@ -239,15 +248,15 @@ __device__ __forceinline__ void tb2_segment(const S* __restrict__ src, S* __rest
         // loads on every path and waits only for the loads at the next row (a guarded store
         // block made it wait for the stores as well, once per row).
         const bool own = out_lane && !wall;
-        R f[9] = {R(b[0]), R(f1), R(a[2]), R(f3), R(c[4]), R(f5), R(f6), R(f7), R(f8)};
-        R g[5] = {R(b[9]), R(g1), R(a[11]), R(g3), R(c[13])};
+        R f[9] = {R(cur[0]), R(f1), R(dn[2]), R(f3), R(up[4]), R(f5), R(f6), R(f7), R(f8)};
+        R g[5] = {R(cur[9]), R(g1), R(dn[11]), R(g3), R(up[13])};
         const Med<R> md = mdb;
         const Mac<R> m = fluid_macros<R>(f, g, md, P);
         if (own)
             step_wall_neighbours<R, PN, S>(
-                med, G, P, x, y, f, g, m, md, [&](int xb, int yb, const R* fb, const R* gb) {
+                med, G, P, x, y, f, g, m, md, [&](int xb, int yb2, const R* fb, const R* gb) {
                     const unsigned ob =
-                        (unsigned(yb) * unsigned(G.pitch) + unsigned(xb)) * B;
+                        (unsigned(yb2) * unsigned(G.pitch) + unsigned(xb)) * B;
 #pragma unroll
                     for (int i = 0; i < 9; ++i) buf_store<S>(S(fb[i]), rd, ob, i * PB);
 #pragma unroll
@@ -265,12 +274,30 @@ __device__ __forceinline__ void tb2_segment(const S* __restrict__ src, S* __rest
         for (int i = 0; i < 5; ++i) buf_store<S>(S(g[i]), rd, vo, sy + (9 + i) * PB);
 #pragma unroll
         for (int i = 0; i < 14; ++i) {
-            a[i] = b[i];
-            b[i] = c[i];
+            bh[i] = cur[i];
+            cur[i] = ah[i];
         }
-        mdb = mdc;
+        mdb = mdn;
         __syncthreads();
-    } while (++y < y1);
+        y += D;
+    } while (y != ye);
+}
+
+// One wavefront's share of a two-step launch: strip `strip` of row segment `seg`.  Adjacent
+// segments sweep in opposite directions (even segments towards increasing y, odd ones towards
+// decreasing y), so that two neighbouring segments read the rows on their common boundary at
+// the same time, at both ends of the sweep: running side by side on one XCD, the second reads
+// them from L2 instead of memory.  (Swept the same way, the second reached those rows ~rows
+// iterations later, after some 2 MB per iteration per XCD had gone through its 4 MB L2.)
+template <typename S, typename R, bool PN>
+__device__ __forceinline__ void tb2_segment(const S* __restrict__ src, S* __restrict__ dst,
+                                            const S* __restrict__ med, const Geo& G,
+                                            const Phys<R>& P, int strip, bool active, int seg,
+                                            int rows) {
+    if (seg & 1)
+        tb2_sweep<S, R, PN, true>(src, dst, med, G, P, strip, active, seg, rows);
+    else
+        tb2_sweep<S, R, PN, false>(src, dst, med, G, P, strip, active, seg, rows);
 }
 
 // Work-groups are dealt round-robin over the 8 XCDs.  This maps a launch's work-group index to a
