@@ -171,8 +171,13 @@ lbm_status lbm_workspace_size(const lbm_params* p, int64_t nsteps_max, size_t* b
 lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const void* phi, const void* K,
                     double phi_uniform, void* workspace, size_t ws_bytes, void* hip_stream);
 
-/* Advance by nsteps time steps (asynchronous).  With a tape, the total number of steps since
- * lbm_init may not exceed the nsteps_max the workspace was sized for (LBM_E_STATE). */
+/* Advance by nsteps time steps (asynchronous).  One time step is the flow collision of
+ * Eq. (17) with the forcing of Eq. (19) and streaming of Eq. (18), coupled to the thermal
+ * collision of Eq. (34) and streaming of Eq. (35), with the macroscopic fields of Eqs. (21)-(23)
+ * and (36) and the wall reconstruction of Sec. 4 (see State semantics); nsteps = 0 does
+ * nothing, nsteps < 0 is LBM_E_INVAL.  With a tape, the total number of steps since lbm_init
+ * may not exceed the nsteps_max the workspace was sized for (LBM_E_STATE).  Launch errors give
+ * LBM_E_HIP; faults inside the steps surface at the next synchronising call. */
 lbm_status lbm_step(lbm_ctx* c, int64_t nsteps);
 
 /* Observables at the current time level (synchronises).  ux, uy, p, T are optional device
@@ -217,13 +222,22 @@ lbm_status lbm_destroy(lbm_ctx* c);
 
 /* ---------------------------------------------------------------------------------------- */
 /* Batched form: many independent cavities of uneven size and parameters stepped together.   */
-/* Every cavity is the model above with its own lbm_params (all of one dtype, no tape) and    */
-/* uniform phi (phi_uniform[i]) and K = Da L^2.                                               */
+/* Every cavity is the model above (the time step of lbm_step, the cavities of Sec. 4) with  */
+/* its own lbm_params (all of one dtype, no tape, pull layout) and uniform phi              */
+/* (phi_uniform[i]) and K = Da L^2 (Sec. 2).  State semantics and fields as above, per cavity. */
 /* ---------------------------------------------------------------------------------------- */
 
+/* Bytes of device workspace lbm_batch_init needs for the n cavities p[0..n-1] (host array).
+ * Errors: LBM_E_INVAL for n <= 0, any cavity lbm_workspace_size would reject, mixed dtypes
+ * or a batch state of 2^31 elements or more; LBM_E_UNSUPPORTED for a tape or the AA layout. */
 lbm_status lbm_batch_workspace_size(int32_t n, const lbm_params* p, size_t* bytes);
 
-/* Create a batch of n cavities.  tune_cache_path: file where the launch shape picked by the
+/* Create a batch of n cavities at rest (the initial state of lbm_init for each).  p and
+ * phi_uniform are host arrays of n entries; the workspace is device memory of at least
+ * lbm_batch_workspace_size() bytes, 256-byte aligned, owned by the caller and kept valid until
+ * lbm_destroy().  Errors as lbm_batch_workspace_size, plus phi_uniform[i] outside (0, 1]
+ * (LBM_E_INVAL), a workspace too small (LBM_E_NOMEM) or a failed device call (LBM_E_HIP).
+ * tune_cache_path: file where the launch shape picked by the
  * autotuner is cached per (device, dtype, cavity set); NULL disables tuning (default shape).
  * The autotuner also times two steps per launch and keeps it where it is faster;
  * p[0].steps_per_launch = 1 or 2 forces one or two (the other cavities' values are ignored;
@@ -233,7 +247,8 @@ lbm_status lbm_batch_init(lbm_ctx** out, int32_t n, const lbm_params* p,
                           const double* phi_uniform, void* workspace, size_t ws_bytes,
                           void* hip_stream, const char* tune_cache_path);
 
-/* Advance every cavity by nsteps (asynchronous; replayed from a captured HIP graph). */
+/* Advance every cavity by nsteps time steps of lbm_step (asynchronous; replayed from a
+ * captured HIP graph).  nsteps < 0 is LBM_E_INVAL. */
 lbm_status lbm_batch_step(lbm_ctx* c, int64_t nsteps);
 
 /* Observables of every cavity (synchronises); o has n entries.  Returns LBM_E_DIVERGED when

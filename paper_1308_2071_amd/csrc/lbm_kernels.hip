@@ -337,9 +337,10 @@ int tb_resident_groups() {
 // Rows per segment of the two-step kernel.  Long segments amortise the two halo rows of the
 // intermediate step; short-lived work-groups let vertically neighbouring segments run close
 // together in time, keep the tail of the launch short, and start with three rows of loads in
-// flight at once.  Measured on the 4096^2 workload (FP32, MLUPS): 4 rows 63.4k, 5 rows 64.5k,
-// 6 rows (12 rounds of the resident set) 65.1k, 8 rows 64.6k, 12 rows 63.5k; one round (69
-// rows) was 10 % slower than 12 rows.
+// flight at once.  Measured on the 4096^2 workload (FP32, MLUPS): 4 rows 68.0k, 5 rows 69.5k,
+// 6 rows (12 rounds of the resident set) 69.1k-70.6k, 8 rows 70.2k, 10 rows 69.3k, 12 rows
+// 68.2k, 16 rows 67.0k, 24 rows 64.4k, one round (69 rows) 58.5k.  (Work-groups of 8 strips
+// instead of 4 measured the same in FP32 and 5 % slower in FP64, 16 strips 5 % slower.)
 int tb_rows(const Geo& G, int nstrips, int resident) {
     const int ngrp = (nstrips + kTbWaves - 1) / kTbWaves;
     const int nseg = resident > 0 ? max(1, kTbRounds * resident / ngrp) : 1;
