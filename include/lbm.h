@@ -213,7 +213,11 @@ lbm_status lbm_grad(lbm_ctx* c, double dJ, void* dJ_dphi, void* dJ_dK);
 lbm_status lbm_state_size(const lbm_ctx* c, size_t* bytes);
 
 /* Copy the state to / from host memory (synchronises).  A loaded state resumes exactly where
- * the saved one stopped.  lbm_load on a context with a tape returns LBM_E_UNSUPPORTED. */
+ * the saved one stopped.  lbm_load on a context with a tape returns LBM_E_UNSUPPORTED.
+ * The saved bytes are a 64-byte header of eight int64 {magic, dtype, nx, ny, row pitch, step,
+ * layout, plane stride} and then the state as the device holds it: 14 planes, each ny rows of
+ * `row pitch` elements with x fastest, planes `plane stride` elements apart.  lbm_load returns
+ * LBM_E_INVAL for a header that does not match the context. */
 lbm_status lbm_save(lbm_ctx* c, void* host_buf, size_t bytes);
 lbm_status lbm_load(lbm_ctx* c, const void* host_buf, size_t bytes);
 

@@ -143,7 +143,7 @@ lbm_status validate(const lbm_params& p) {
         return fail(LBM_E_INVAL, "grid %d x %d too small (need >= %d x %d)", p.nx, p.ny, minx,
                     miny);
     const long long pitch = (p.nx + kPitchAlign - 1) / kPitchAlign * kPitchAlign;
-    if (pitch * (long long)p.ny * kPlanes >= (1LL << 31))
+    if (plane_elems(pitch, p.ny) * kPlanes >= (1LL << 31))
         return fail(LBM_E_INVAL, "grid %d x %d exceeds the 2^31-element state limit", p.nx, p.ny);
     if (!(p.rho0 > 0) || !(p.sigma > 0) || !(p.J > 0))
         return fail(LBM_E_INVAL, "rho0, sigma and J must be positive");
@@ -160,7 +160,7 @@ lbm_status validate(const lbm_params& p) {
     if (p.steps_per_launch < 0 || p.steps_per_launch > 2)
         return fail(LBM_E_INVAL, "steps_per_launch = %d is not 0, 1 or 2", p.steps_per_launch);
     if (p.steps_per_launch == 2 &&
-        pitch * (long long)p.ny * kPlanes * (long long)storage_bytes(p.dtype) >= (1LL << 31))
+        plane_elems(pitch, p.ny) * kPlanes * (long long)storage_bytes(p.dtype) >= (1LL << 31))
         return fail(LBM_E_UNSUPPORTED, "two steps per launch need a state below 2 GiB");
     if (p.layout == LBM_LAYOUT_AA && p.checkpoint_every > 0)
         return fail(LBM_E_UNSUPPORTED, "the AA layout has no adjoint tape");
@@ -183,7 +183,7 @@ Geo make_geo(const lbm_params& p) {
     G.nx = p.nx;
     G.ny = p.ny;
     G.pitch = (p.nx + kPitchAlign - 1) / kPitchAlign * kPitchAlign;
-    G.plane = G.pitch * p.ny;
+    G.plane = int(plane_elems(G.pitch, p.ny));
     G.wallW = walled(p, LBM_WEST);
     G.wallE = walled(p, LBM_EAST);
     G.wallS = walled(p, LBM_SOUTH);
@@ -1146,14 +1146,15 @@ lbm_status lbm_state_size(const lbm_ctx* c, size_t* bytes) {
     return LBM_OK;
 }
 
-// Saved layout: 64-byte header {magic, dtype, nx, ny, pitch, step} then the raw buffer.
+// Saved layout: 64-byte header {magic, dtype, nx, ny, pitch, step, layout, plane stride} then
+// the raw buffer.
 lbm_status lbm_save(lbm_ctx* c, void* host_buf, size_t bytes) {
     lbm_status s = check_ctx(c, false);
     if (s != LBM_OK) return s;
     if (!host_buf || bytes < c->L.state_bytes + 64)
         return fail(LBM_E_INVAL, "buffer of %zu bytes < %zu", bytes, c->L.state_bytes + 64);
     int64_t hdr[8] = {0x4C424D50, c->p.dtype, c->p.nx, c->p.ny, c->G.pitch, c->step, c->p.layout,
-                      0};
+                      c->G.plane};
     std::memcpy(host_buf, hdr, sizeof hdr);
     HIP_TRY(hipMemcpyAsync((char*)host_buf + 64, c->buf(c->cur), c->L.state_bytes,
                            hipMemcpyDeviceToHost, c->stream),
@@ -1172,7 +1173,7 @@ lbm_status lbm_load(lbm_ctx* c, const void* host_buf, size_t bytes) {
     int64_t hdr[8];
     std::memcpy(hdr, host_buf, sizeof hdr);
     if (hdr[0] != 0x4C424D50 || hdr[1] != c->p.dtype || hdr[2] != c->p.nx || hdr[3] != c->p.ny ||
-        hdr[4] != c->G.pitch || hdr[6] != c->p.layout || hdr[5] < 0)
+        hdr[4] != c->G.pitch || hdr[6] != c->p.layout || hdr[7] != c->G.plane || hdr[5] < 0)
         return fail(LBM_E_INVAL, "saved state does not match this context");
     HIP_TRY(hipMemcpyAsync(c->buf(c->cur), (const char*)host_buf + 64, c->L.state_bytes,
                            hipMemcpyHostToDevice, c->stream),

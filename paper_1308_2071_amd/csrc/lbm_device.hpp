@@ -9,7 +9,7 @@
 // With deviations, m' = M f' and the rest moments rho0 (1, -2, 1, 0, ..., 0) drop out; the
 // pressure enters through P = phi p - rho0 cs^2.
 //
-// Layout: 14 planes [f0..f8, g0..g4], each [ny][pitch] with x fastest.
+// Layout: 14 planes [f0..f8, g0..g4], each [ny][pitch] with x fastest, G.plane elements apart.
 //
 // Precision: S is the storage type of the populations and the medium planes, R the type the
 // arithmetic runs in.  (S, R) = (float, float), (double, double), or (float, double): FP32
@@ -30,7 +30,7 @@ constexpr double kErgun = 0.14288690166235207;
 
 struct Geo {
     int nx, ny, pitch;
-    int plane;             // elements per plane, ny * pitch
+    int plane;             // elements from one plane to the next: ny * pitch plus a pad
     int wallW, wallE, wallS, wallN;  // side is a wall (not periodic)
 };
 

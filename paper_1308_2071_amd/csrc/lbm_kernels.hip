@@ -334,13 +334,16 @@ int tb_resident_groups() {
     return n;
 }
 
-// Rows per segment of the two-step kernel.  Long segments amortise the two halo rows of the
-// intermediate step; short-lived work-groups let vertically neighbouring segments run close
-// together in time, keep the tail of the launch short, and start with three rows of loads in
-// flight at once.  Measured on the 4096^2 workload (FP32, MLUPS): 4 rows 68.0k, 5 rows 69.5k,
-// 6 rows (12 rounds of the resident set) 69.1k-70.6k, 8 rows 70.2k, 10 rows 69.3k, 12 rows
-// 68.2k, 16 rows 67.0k, 24 rows 64.4k, one round (69 rows) 58.5k.  (Work-groups of 8 strips
-// instead of 4 measured the same in FP32 and 5 % slower in FP64, 16 strips 5 % slower.)
+// Rows per segment of the two-step kernel.  Each segment reads the intermediate step's two
+// halo rows and one row past its end on top of its own rows; neighbouring segments, which sweep
+// towards each other, find some of those rows in L2.  Longer segments fetch less but live
+// longer, and the launch's tail, in which the last work-groups finish on a partly idle device,
+// grows with them.  Measured on the 4096^2 workload (FP32, MLUPS; fetched bytes over one read
+// of the 16 planes): 5 rows 70.6k, 6 rows (12 rounds of the resident set) 71.6k and 1.36x,
+// 11 rows 1.29x, 17 rows 1.24x, 23 rows (3 rounds) 65.2k and 1.21x, 35 rows 1.17x, 69 rows
+// (one round) 1.12x.  (Work-groups of 8 strips instead of 4 measured the same in FP32 and 5 %
+// slower in FP64, 16 strips 5 % slower; a work-group of two vertically adjacent segments, 8
+// wavefronts, fetched and ran the same as two work-groups of one.)
 int tb_rows(const Geo& G, int nstrips, int resident) {
     const int ngrp = (nstrips + kTbWaves - 1) / kTbWaves;
     const int nseg = resident > 0 ? max(1, kTbRounds * resident / ngrp) : 1;

@@ -226,11 +226,14 @@ __device__ __forceinline__ void tb2_sweep(const S* __restrict__ src, S* __restri
         for (int i = 0; i < 14; ++i) buf_store<S>(S(0), rd, kBufOutOfRange, i * PB);
     }
     // yb != ye on every segment; the work-group's waves run the same rows
+    // the last row's loads would fetch a row that nothing uses: out of range, they return zero
+    // without a memory access
+    const TbCols none = {kBufOutOfRange, kBufOutOfRange, kBufOutOfRange, kBufOutOfRange};
     int y = yb;
     do {
         tb_finish<S, R, PN>(raw, G, P, x, tb_row(G, y + D), ah, mdn);
         // issue the next row's loads now; they complete during this row's work
-        tb_load<S, PN>(rs, rm, G, PB, RB, cols, tb_row(G, y + 2 * D), raw);
+        tb_load<S, PN>(rs, rm, G, PB, RB, y + D == ye ? none : cols, tb_row(G, y + 2 * D), raw);
         // step n+1 at rows y - 1 and y + 1, whichever way the sweep runs
         const S* dn = REV ? ah : bh;   // row y - 1
         const S* up = REV ? bh : ah;   // row y + 1

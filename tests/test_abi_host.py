@@ -156,7 +156,8 @@ def test_workspace_grows_with_tape(lbm):
 def test_aa_layout_halves_the_state_memory(lbm):
     pull = lbm.lbm_workspace_size(lbm.make_params(nx=300, ny=200), 0)
     aa = lbm.lbm_workspace_size(lbm.make_params(nx=300, ny=200, layout="aa"), 0)
-    state = 14 * 200 * 320 * 4       # pitch 320 = 300 rounded up to 64
+    # pitch 320 = 300 rounded up to 64; the planes lie 200 rows plus a pad of 1056 elements apart
+    state = 14 * (200 * 320 + 1056) * 4
     assert pull - aa == state
 
 

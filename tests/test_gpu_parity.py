@@ -182,7 +182,7 @@ def test_divergence_is_reported():
     cav.step(10)
     assert not cav.observables(False)["diverged"]
     snap = cav.save()
-    pitch = 64
+    pitch = int(snap[:64].view(np.int64)[4])
     off = 64 + (5 * pitch + 5) * 4          # plane f0, node (5, 5), after the 64-byte header
     snap[off:off + 4] = np.frombuffer(np.float32(np.nan).tobytes(), dtype=np.uint8)
     cav.load(snap)
@@ -198,7 +198,8 @@ def test_overflowing_velocity_is_reported():
     params = dict(nx=16, ny=16, Ra=1e4, Pr=0.71, Da=1e-2, dtype="fp64")
     cav = Cavity(params, phi_uniform=0.6)
     snap = cav.save()
-    pitch, plane = 64, 64 * 16
+    hdr = snap[:64].view(np.int64)          # {magic, dtype, nx, ny, pitch, step, layout, stride}
+    pitch, plane = int(hdr[4]), int(hdr[7])
     st = snap[64:].view(np.float64)
     st[1 * plane + 8 * pitch + 8] = 1e200
     st[3 * plane + 8 * pitch + 10] = -1e200
