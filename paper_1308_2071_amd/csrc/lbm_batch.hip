@@ -105,7 +105,7 @@ hipError_t launch_batch_step(const void* src, void* dst, const BatchTable<R>& T,
 // one list: wg_cav[w] is the cavity of logical work-group w, and for that cavity C.tile0 is its
 // first logical work-group and C.tiles_x its number of strip groups.
 template <typename S, typename R, int TW>
-__global__ __launch_bounds__(64 * TW) void batch_tb2_kernel(
+__global__ __launch_bounds__(64 * TW, (tb_min_waves<S, R>())) void batch_tb2_kernel(
     const S* __restrict__ src, S* __restrict__ dst, const BatchCavity* __restrict__ cav,
     const Phys<R>* __restrict__ phys, const int* __restrict__ wg_cav, int rows, int chunk) {
     const int wg = tb_logical_group(chunk);

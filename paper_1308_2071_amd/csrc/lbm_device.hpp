@@ -240,14 +240,19 @@ __device__ __forceinline__ Mac<R> fluid_macros(const R f[9], const R g[5], const
                                                const Phys<R>& P) {
     const Vel<R> v = velocity<R>(f, g, md, P);
     Mac<R> m;
-    const R sum18 = ((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8]));
-    // phi p = cs^2/(1 - w0) [sum_{i>=1} f_i + rho0 s0(u)], s0 = -w0 |u|^2 / (2 phi cs^2);
-    // cs^2/(1 - w0) = 3/5 is applied as a correctly rounded division by 5: a product with the
-    // rounded 0.6 (1 + 4e-8 in FP32) is a common gain on the pressure level, which no
-    // equation restores (it is a gauge); in the 256^2 workload it moved the FP32 pressure by
-    // 3.0e-4 of its range in 50k steps, against 1.2e-4 with the division
-    m.P = div_const(R(3) * fma(R(-2.0 / 3.0) * P.rho0, v.uu * md.inv_phi, sum18), R(5),
-                    R(1.0 / 5.0));
+    // phi p = cs^2/(1 - w0) [sum_{i>=1} f_i + rho0 s0(u)], s0 = -w0 |u|^2 / (2 phi cs^2).
+    // The level of phi p is a free mode of the step (a gauge that no equation restores), so
+    // each rounding on its path that repeats step after step moves it for good.  The sum and
+    // the factor are taken in FP64 in every precision and rounded once: in the 256^2 workload
+    // the FP32 level moved by 1.2e-4 of p's range in 50k steps with them in FP32, 7.3e-5 this
+    // way, at no measurable cost.  cs^2/(1 - w0) = 3/5 is a correctly rounded division by 5:
+    // a product with the rounded 0.6 is a common gain on the level (in FP32 it moved it by
+    // 3.0e-4 of the range).
+    const double sum18 = ((double(f[1]) + double(f[2])) + (double(f[3]) + double(f[4]))) +
+                         ((double(f[5]) + double(f[6])) + (double(f[7]) + double(f[8])));
+    m.P = R(div_const(3.0 * fma(-2.0 / 3.0 * double(P.rho0), double(v.uu) * double(md.inv_phi),
+                                sum18),
+                      5.0, 1.0 / 5.0));
     m.theta = v.theta;
     m.ux = v.ux;
     m.uy = v.uy;

@@ -28,6 +28,13 @@ constexpr int kTbCols = 62;
 constexpr int kTbWaves = 4;
 constexpr int kTbRounds = 12;
 constexpr int kTbMinRows = 6;
+// Minimum wavefronts per SIMD the two-step kernels are compiled for: in FP32 four, the
+// occupancy their ~128 registers allow (the compiler would otherwise settle for 129 registers
+// and three); the FP64-arithmetic forms take what their registers give.
+template <typename S, typename R>
+constexpr int tb_min_waves() {
+    return sizeof(S) == 4 && sizeof(R) == 4 ? 4 : 1;
+}
 
 // The two-step kernels address a state (the 14 planes) through one raw buffer descriptor and
 // drop stores through an offset of 2^31 past it: they need a state below 2^31 bytes.

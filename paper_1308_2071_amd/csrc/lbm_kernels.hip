@@ -66,7 +66,7 @@ __global__ __launch_bounds__(kTileX) void aa_step_kernel(S* __restrict__ buf,
 }
 
 template <typename S, typename R, bool PN>
-__global__ __launch_bounds__(64 * kTbWaves) void tb2_step_kernel(const S* __restrict__ src,
+__global__ __launch_bounds__(64 * kTbWaves, (tb_min_waves<S, R>())) void tb2_step_kernel(const S* __restrict__ src,
                                                                  S* __restrict__ dst,
                                                                  const S* __restrict__ med,
                                                                  Geo G, Phys<R> P, int nstrips,
