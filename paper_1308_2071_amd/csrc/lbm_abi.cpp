@@ -530,7 +530,7 @@ lbm_status batch_layout(int32_t n, const lbm_params* p, BatchLayout* L) {
     L->off_cav2 = o;
     o += align_up(n * sizeof(BatchCavity));
     L->off_tbwg = o;
-    L->max_tbwg = batch_tb_groups(geos, kTbMinRows, 1);   // the most: shortest rows, 1 strip
+    L->max_tbwg = batch_tb_groups(geos, kBatchTbMinRows, 1);  // the most: shortest rows, 1 strip
     o += align_up(L->max_tbwg * sizeof(int));
     L->off_part = o;
     o += align_up(size_t(n) * kBatchObsPer * sizeof(double));
@@ -605,7 +605,7 @@ hipError_t batch_tb_tables(lbm_ctx* c, int rows, int waves) {
         cav[i].tiles_x = ngrp;
         wc.insert(wc.end(), size_t(ngrp) * size_t((G.ny + rows - 1) / rows), i);
     }
-    if (rows < kTbMinRows || wc.size() > c->b_max_tbwg) return hipErrorInvalidValue;
+    if (rows < kBatchTbMinRows || wc.size() > c->b_max_tbwg) return hipErrorInvalidValue;
     c->b_tb_nwg = int(wc.size());
     hipError_t e = hipMemcpy(c->ws + c->b_off_cav2, cav.data(), cav.size() * sizeof(BatchCavity),
                              hipMemcpyHostToDevice);
@@ -758,8 +758,10 @@ hipError_t time_steps(lbm_ctx* c, hipEvent_t e0, hipEvent_t e1, int steps_per_la
 
 // Autotuner, on the batch itself.  The one-step kernel: every supported tile shape (rows per
 // work-group x 64-node segments per work-item), with one tile per work-group and with chunked
-// persistent grids of 2..16 work-groups per CU.  The two-step kernel: segments of 6, 8, 12,
-// 16 and 24 rows with 1, 2 or 4 strips per work-group.  It keeps the fastest per step (the
+// persistent grids of 2..16 work-groups per CU.  The two-step kernel: segments of 2, 3, 4, 5,
+// 6, 8 and 12 rows with 1, 2 or 4 strips per work-group (short segments keep the launch's
+// tail short; on the 64-cavity workload 3 rows and one strip won, 61.4k against 60.3k MLUPS
+// for the best of 6 rows and up).  It keeps the fastest per step (the
 // one-step shape is kept either way, for odd step counts), unless steps_per_launch of the
 // first cavity forces one or two steps per launch.  The result is cached per (device, dtype,
 // cavity shapes, that setting) in tune_cache_path.
@@ -800,7 +802,7 @@ lbm_status batch_tune(lbm_ctx* c, const char* path) {
     const int shapes[10][2] = {{1, 1}, {1, 2}, {1, 4}, {2, 1}, {2, 2}, {2, 4},
                                {4, 1}, {4, 2}, {4, 4}, {8, 1}};
     const int per_cu[5] = {0, 2, 4, 8, 16};  // 0: one tile per work-group
-    const int tb_rows[5] = {6, 8, 12, 16, 24};
+    const int tb_rows[7] = {kBatchTbMinRows, 3, 4, 5, 6, 8, 12};
     const int tb_waves[3] = {1, 2, 4};
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "event");

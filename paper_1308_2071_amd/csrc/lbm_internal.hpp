@@ -28,6 +28,8 @@ constexpr int kTbCols = 62;
 constexpr int kTbWaves = 4;
 constexpr int kTbRounds = 12;
 constexpr int kTbMinRows = 6;
+// The shortest segment the batch's autotuner tries.
+constexpr int kBatchTbMinRows = 2;
 // Minimum wavefronts per SIMD the two-step kernels are compiled for: in FP32 four, the
 // occupancy their ~128 registers allow (the compiler would otherwise settle for 129 registers
 // and three); the FP64-arithmetic forms take what their registers give.

@@ -101,7 +101,7 @@ def test_autotuner_caches_its_choice(tmp_path):
     assert len(lines) == 1 and len(lines[0].split()) == 6
     key = lines[0].split()[0].split("|")
     assert key[0] == "v3" and key[1].startswith(("gfx", "unknown")) and key[2] == "fp32"
-    assert key[4] == "s0" and int(lines[0].split()[4]) in (0, 6, 8, 12, 16, 24)
+    assert key[4] == "s0" and int(lines[0].split()[4]) in (0, 2, 3, 4, 5, 6, 8, 12)
     assert int(lines[0].split()[5]) in (1, 2, 4)
     b = Batch(params, phis, tune_cache_path=path)       # served from the cache
     assert b.shape() == shape
@@ -112,6 +112,35 @@ def test_autotuner_caches_its_choice(tmp_path):
     wg, npt = shape[1], shape[0]
     assert wg in (64, 128, 256, 512) and npt in (1, 2, 4) and shape[3] % 2 == 0
     assert shape[4] in (1, 2) and (shape[5] > 0) == (shape[4] == 2)
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+def test_every_two_step_shape_the_tuner_tries_equals_standalone_runs(dtype, tmp_path):
+    """Every segment height (2, 3, 4, 5, 6, 8, 12 rows) and strip count (1, 2, 4 per
+    work-group) the autotuner may pick, forced through its cache file, steps each cavity
+    bitwise like its own plain run (odd step count: graph replays, then one single step)."""
+    params, phis = small_batch(dtype)
+    params[0] = dict(params[0], steps_per_launch=2)
+    path = tmp_path / "tune.txt"
+    Batch(params, phis, tune_cache_path=str(path)).close()
+    line = path.read_text().split()
+    want = []
+    for p, phi in zip(params, phis):
+        c = Cavity(p, phi_uniform=phi)
+        c.step(77)
+        want.append(c.observables())
+        c.close()
+    for rows in (2, 3, 4, 5, 6, 8, 12):
+        for strips in (1, 2, 4):
+            path.write_text(" ".join(line[:4] + [str(rows), str(strips)]) + "\n")
+            b = Batch(params, phis, tune_cache_path=str(path))
+            assert b.shape()[5] == rows, (rows, b.shape())
+            b.step(77)
+            for i, ref_obs in enumerate(want):
+                got = b.fields(i)
+                for k in FIELDS:
+                    assert torch.equal(got[k], ref_obs[k]), (rows, strips, i, k)
+            b.close()
 
 
 def test_batch_rejects_mixed_dtypes_and_tapes():
