@@ -42,6 +42,7 @@ TRAFFIC_PROFILES = {
 }
 STEP_SOURCES = ("paper_1308_2071_amd/csrc/lbm_device.hpp", "paper_1308_2071_amd/csrc/lbm_tb2.hpp",
                 "paper_1308_2071_amd/csrc/lbm_kernels.hip",
+                "paper_1308_2071_amd/csrc/lbm_internal.hpp",
                 "paper_1308_2071_amd/build.py")
 
 
