@@ -117,6 +117,14 @@ def test_invalid_parameters_are_rejected(lbm, bad):
     assert lbm.lbm_last_error() != ""
 
 
+def test_state_limit_is_exact(lbm):
+    """The 2^31-element state limit counts the 14 planes as they lie in memory: ny rows of the
+    pitch (nx rounded up to 64) plus the pad between planes.  12354^2 (pitch 12416, 14 x
+    (12416 x 12354 + 1056) = 2,147,436,480 elements) is the largest square grid under it."""
+    assert status_of(lbm, nx=12354, ny=12354, dtype=1) == 0
+    assert status_of(lbm, nx=12355, ny=12355, dtype=1) == -1
+
+
 def test_init_rejects_before_any_device_call(lbm):
     from paper_1308_2071_amd import _abi
     L = _abi.library()

@@ -8,7 +8,7 @@
 - roofline4096 (4096 x 4096, per-node phi and K, FP32 storage with FP32 or FP64 arithmetic): the
   first 10 steps against the oracle on the full field, and a 512 x 512 crop of the same medium
   for 2000 steps (FP64 arithmetic on FP32 storage is held to 1e-5 of range and Nu to 1e-4);
-- the largest square grid the 2^31-element state limit allows (12352^2, FP64): two steps
+- the largest square grid the 2^31-element state limit allows (12354^2, FP64): two steps
   against the oracle at every node;
 - two steps per launch at full size: bitwise equal to single steps over 1000 steps of the
   roofline4096 field (FP32 and FP64 arithmetic), and for FP64 storage at 4096^2, a state near
@@ -175,10 +175,10 @@ def test_fp64_4096_fused_state_near_the_2_gib_limit_equals_single_steps():
 
 
 def test_largest_grid_the_state_limit_allows_fp64_against_oracle():
-    """The largest square grid under the 2^31-element state limit (12352^2, 14 planes of
-    152.6M nodes; FP64 planes of 1.22 GB, the largest 32-bit byte offsets any kernel forms),
+    """The largest square grid under the 2^31-element state limit (12354^2, 14 planes of
+    152.6M nodes; FP64 planes of 1.23 GB, the largest 32-bit byte offsets any kernel forms),
     uniform medium, two steps: every node against the FP64 oracle at 1e-12."""
-    n = 12352
+    n = 12354
     params = workloads.cavity(n, Ra=1e6, Pr=0.71, Da=1e-3)
     cav = Cavity(dict(params, dtype="fp64"), phi_uniform=0.6)
     cav.step(2)
