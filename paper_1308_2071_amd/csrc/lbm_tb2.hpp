@@ -225,10 +225,10 @@ __device__ __forceinline__ void tb2_sweep(const S* __restrict__ src, S* __restri
 #pragma unroll
         for (int i = 0; i < 14; ++i) buf_store<S>(S(0), rd, kBufOutOfRange, i * PB);
     }
-    // yb != ye on every segment; the work-group's waves run the same rows
     // the last row's loads would fetch a row that nothing uses: out of range, they return zero
     // without a memory access
     const TbCols none = {kBufOutOfRange, kBufOutOfRange, kBufOutOfRange, kBufOutOfRange};
+    // yb != ye on every segment; the work-group's waves run the same rows
     int y = yb;
     do {
         tb_finish<S, R, PN>(raw, G, P, x, tb_row(G, y + D), ah, mdn);
