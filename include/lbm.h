@@ -100,12 +100,15 @@ typedef struct {
     int32_t dtype;           /* LBM_FP32, LBM_FP64 or LBM_FP32_F64                            */
     int32_t checkpoint_every;/* 0: no adjoint tape; C > 0: checkpoint every C steps, lbm_grad on */
     int32_t layout;          /* LBM_LAYOUT_PULL (default) or LBM_LAYOUT_AA                     */
-    int32_t steps_per_launch;/* 0 (default): fuse two time steps per launch where that is     */
-                             /* faster (large grids, storage type = arithmetic type); 2: fuse */
-                             /* wherever the pull layout without a tape allows; 1: one step  */
-                             /* per launch.  Results are bitwise the same in every case.      */
-                             /* Fusing needs a state (14 planes) below 2 GiB: 2 beyond it    */
-                             /* gives LBM_E_UNSUPPORTED, 0 steps one at a time.               */
+    int32_t steps_per_launch;/* Time steps per launch of the pull layout.  0 (default): two  */
+                             /* (the intermediate step kept in registers) where that is      */
+                             /* faster (large grids, storage type = arithmetic type), four   */
+                             /* (16 x 16 tiles advanced in LDS) where that is (small grids), */
+                             /* else one.  1: one.  2: two, wherever the pull layout without */
+                             /* a tape allows; it needs a state (14 planes) below 2 GiB and  */
+                             /* gives LBM_E_UNSUPPORTED beyond.  4: four (with a tape, only  */
+                             /* between checkpoints).  The AA layout steps one at a time.    */
+                             /* Results are bitwise the same in every case.                  */
 } lbm_params;
 
 /* Reasons for the divergence flag (bits of lbm_obs.why).  The paper gives no divergence test;
@@ -194,10 +197,10 @@ lbm_status lbm_observables(lbm_ctx* c, lbm_obs* o, void* ux, void* uy, void* p, 
  * L sqrt(g beta dT L) is the psi_max of Sec. 4.2 (Table 3). */
 lbm_status lbm_stream_function(lbm_ctx* c, void* psi);
 
-/* Launch shape of the time loop in use (no device work): out[0] time steps per launch (1, or
- * 2 when two steps are fused, see steps_per_launch), out[1] the layout (LBM_LAYOUT_*),
- * out[2] rows per wavefront segment of the fused kernel (0 when not fused), out[3]
- * work-groups per launch.  out holds 4 entries. */
+/* Launch shape of the time loop in use (no device work): out[0] time steps per launch (1, 2
+ * or 4, see steps_per_launch), out[1] the layout (LBM_LAYOUT_*), out[2] rows per wavefront
+ * segment of the two-step kernel, or the tile side (16) of the four-step one (0 for one step
+ * per launch), out[3] work-groups per launch.  out holds 4 entries. */
 lbm_status lbm_step_shape(const lbm_ctx* c, int32_t* out);
 
 /* Discrete adjoint (synchronises).  For J = nu_hot at the current time level n (Eq. (38)),
@@ -246,7 +249,8 @@ lbm_status lbm_batch_workspace_size(int32_t n, const lbm_params* p, size_t* byte
  * The autotuner also times two steps per launch and keeps it where it is faster;
  * p[0].steps_per_launch = 1 or 2 forces one or two (the other cavities' values are ignored;
  * 2 gives LBM_E_UNSUPPORTED if a cavity's state reaches 2 GiB, where the autotuner keeps one
- * step per launch).  Results are bitwise the same either way. */
+ * step per launch; 4, the tiles of a single cavity, gives LBM_E_UNSUPPORTED).  Results are
+ * bitwise the same either way. */
 lbm_status lbm_batch_init(lbm_ctx** out, int32_t n, const lbm_params* p,
                           const double* phi_uniform, void* workspace, size_t ws_bytes,
                           void* hip_stream, const char* tune_cache_path);

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "liblbmpm.so")
-SOURCES = ["lbm_abi.cpp", "lbm_kernels.hip", "lbm_adjoint.hip", "lbm_batch.hip"]
+SOURCES = ["lbm_abi.cpp", "lbm_kernels.hip", "lbm_tile.hip", "lbm_adjoint.hip", "lbm_batch.hip"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -157,8 +157,10 @@ lbm_status validate(const lbm_params& p) {
     if (p.checkpoint_every < 0) return fail(LBM_E_INVAL, "checkpoint_every must be >= 0");
     if (p.layout != LBM_LAYOUT_PULL && p.layout != LBM_LAYOUT_AA)
         return fail(LBM_E_INVAL, "layout %d is not LBM_LAYOUT_PULL or LBM_LAYOUT_AA", p.layout);
-    if (p.steps_per_launch < 0 || p.steps_per_launch > 2)
-        return fail(LBM_E_INVAL, "steps_per_launch = %d is not 0, 1 or 2", p.steps_per_launch);
+    if (p.steps_per_launch != 0 && p.steps_per_launch != 1 && p.steps_per_launch != 2 &&
+        p.steps_per_launch != kTileSteps)
+        return fail(LBM_E_INVAL, "steps_per_launch = %d is not 0, 1, 2 or %d", p.steps_per_launch,
+                    kTileSteps);
     if (p.steps_per_launch == 2 &&
         plane_elems(pitch, p.ny) * kPlanes * (long long)storage_bytes(p.dtype) >= (1LL << 31))
         return fail(LBM_E_UNSUPPORTED, "two steps per launch need a state below 2 GiB");
@@ -391,24 +393,32 @@ hipError_t advance(lbm_ctx* c, int from, hipStream_t s) {
     });
 }
 
-// Two steps in one launch from buffer `from` (pull layout only).
-hipError_t advance2(lbm_ctx* c, int from, hipStream_t s) {
+// k > 1 steps in one launch from buffer `from` (pull layout only): the two-step kernel for
+// k = 2, the tiles in LDS for k = kTileSteps.
+hipError_t advance_k(lbm_ctx* c, int k, int from, hipStream_t s) {
     return with_types(c->p.dtype, [&](auto st, auto rt) {
         LBM_TYPES(st, rt)
-        return launch_tb2_step<S, R>(c->buf(from), c->buf(1 - from), c->medp(), c->G,
-                                     phys<R>(c), s);
+        if (k == 2)
+            return launch_tb2_step<S, R>(c->buf(from), c->buf(1 - from), c->medp(), c->G,
+                                         phys<R>(c), s);
+        return launch_tile_step<S, R>(c->buf(from), c->buf(1 - from), c->medp(), c->G,
+                                      phys<R>(c), s);
     });
 }
 
-// Whether the time loop fuses two steps per launch: never with the AA layout or a tape, always
-// when asked for (steps_per_launch = 2), and by default where it is measured to pay.
-bool fused(const lbm_ctx* c) {
-    if (c->p.layout != LBM_LAYOUT_PULL || c->p.checkpoint_every != 0) return false;
-    if (c->p.steps_per_launch == 1) return false;
-    if (c->p.steps_per_launch == 2) return true;
+// Time steps per launch of the time loop: one with the AA layout; steps_per_launch when it
+// asks for 1, 2 or kTileSteps; by default two (the two-step kernel) where that is measured to
+// pay, else kTileSteps (the tiles in LDS) where that is, else one.  With a tape the two-step
+// kernel is not used, and the tiles only between checkpoints (lbm_step).
+int launch_steps(const lbm_ctx* c) {
+    if (c->p.layout != LBM_LAYOUT_PULL) return 1;
+    const bool tape = c->p.checkpoint_every != 0;
+    if (c->p.steps_per_launch != 0)
+        return tape && c->p.steps_per_launch == 2 ? 1 : c->p.steps_per_launch;
     return with_types(c->p.dtype, [&](auto st, auto rt) {
         LBM_TYPES(st, rt)
-        return tb2_pays<S, R>(c->G, c->med);
+        if (!tape && tb2_pays<S, R>(c->G, c->med)) return 2;
+        return tile_pays<S, R>(c->G, c->med) ? kTileSteps : 1;
     });
 }
 
@@ -428,10 +438,11 @@ lbm_status ensure_graph(lbm_ctx* c, int start) {
     HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal), "begin capture");
     hipError_t err = hipSuccess;
     int b = start;
-    if (fused(c)) {
-        // kGraphSteps / 2 launches: an even number of buffer swaps
-        for (int k = 0; k < kGraphSteps / 2 && err == hipSuccess; ++k) {
-            err = advance2(c, b, c->cap);
+    const int k = launch_steps(c);
+    if (k > 1) {
+        // kGraphSteps / k launches: an even number of buffer swaps
+        for (int n = 0; n < kGraphSteps / k && err == hipSuccess; ++n) {
+            err = advance_k(c, k, b, c->cap);
             b = 1 - b;
         }
     } else {
@@ -499,6 +510,8 @@ lbm_status batch_layout(int32_t n, const lbm_params* p, BatchLayout* L) {
             return fail(LBM_E_UNSUPPORTED, "cavity %d: no adjoint tape in a batch", i);
         if (p[i].layout != LBM_LAYOUT_PULL)
             return fail(LBM_E_UNSUPPORTED, "cavity %d: a batch uses the pull layout", i);
+        if (i == 0 && p[0].steps_per_launch == kTileSteps)
+            return fail(LBM_E_UNSUPPORTED, "a batch steps one or two steps per launch");
         const Geo G = make_geo(p[i]);
         if (p[0].steps_per_launch == 2 && !tb2_fits(G, storage_bytes(dt)))
             return fail(LBM_E_UNSUPPORTED,
@@ -1100,21 +1113,25 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
             c->step += kGraphSteps;
         }
     }
-    if (fused(c)) {
-        for (; left >= 2; left -= 2) {
-            HIP_TRY(advance2(c, c->cur, c->stream), "step launch");
-            c->cur = 1 - c->cur;
-            c->step += 2;
-        }
-    }
-    for (; left > 0; --left) {
+    // k steps per launch where they fit: with a tape, between checkpoints (the state at every
+    // multiple of C goes to its checkpoint first)
+    const int k = launch_steps(c);
+    while (left > 0) {
         if (C > 0 && c->step % C == 0)
             HIP_TRY(hipMemcpyAsync(c->ckpt(size_t(c->step / C)), c->buf(c->cur),
                                    c->L.state_bytes, hipMemcpyDeviceToDevice, c->stream),
                     "checkpoint copy");
-        HIP_TRY(advance(c, c->cur, c->stream), "step launch");
+        const int64_t room = C > 0 ? C - c->step % C : left;   // steps to the next checkpoint
+        if (k > 1 && left >= k && room >= k) {
+            HIP_TRY(advance_k(c, k, c->cur, c->stream), "step launch");
+            c->step += k;
+            left -= k;
+        } else {
+            HIP_TRY(advance(c, c->cur, c->stream), "step launch");
+            c->step += 1;
+            left -= 1;
+        }
         c->cur = 1 - c->cur;
-        c->step += 1;
     }
     return LBM_OK;
 }
@@ -1471,12 +1488,16 @@ lbm_status lbm_step_shape(const lbm_ctx* c, int32_t* out) {
     lbm_status s = check_ctx(c, false);
     if (s != LBM_OK) return s;
     if (!out) return fail(LBM_E_INVAL, "null argument");
-    const bool f = fused(c);
-    out[0] = f ? 2 : 1;
+    const int k = launch_steps(c);
+    out[0] = k;
     out[1] = c->p.layout;
     out[2] = 0;
     out[3] = (c->G.nx + kTileX - 1) / kTileX * c->G.ny;
-    if (f)
+    if (k == kTileSteps) {
+        out[2] = kTileSide;
+        out[3] = (c->G.nx + kTileSide - 1) / kTileSide * ((c->G.ny + kTileSide - 1) / kTileSide);
+    }
+    if (k == 2)
         (void)with_types(c->p.dtype, [&](auto st, auto rt) {
             LBM_TYPES(st, rt)
             int rows = 0, nwg = 0;
@@ -1527,11 +1548,12 @@ lbm_status lbm_run_noalloc(const lbm_params* p, const void* phi, const void* K,
     s = setup_ctx(&c, *p, L, 0, phi, K, phi_uniform, ws, hip_stream);
     if (s != LBM_OK) return s;
     int64_t left = nsteps;
-    if (fused(&c)) {
-        for (; left >= 2; left -= 2) {
-            HIP_TRY(advance2(&c, c.cur, c.stream), "step launch");
+    const int k = launch_steps(&c);
+    if (k > 1) {
+        for (; left >= k; left -= k) {
+            HIP_TRY(advance_k(&c, k, c.cur, c.stream), "step launch");
             c.cur = 1 - c.cur;
-            c.step += 2;
+            c.step += k;
         }
     }
     for (; left > 0; --left) {

@@ -38,6 +38,12 @@ constexpr int tb_min_waves() {
     return sizeof(S) == 4 && sizeof(R) == 4 ? 4 : 1;
 }
 
+// Several steps per launch on small grids (lbm_tile.hip): tile side, steps per launch and
+// threads per work-group.
+constexpr int kTileSide = 16;
+constexpr int kTileSteps = 4;
+constexpr int kTileThreads = 640;   // one work-item per node of the largest region (25^2)
+
 // The two-step kernels address a state (the 14 planes) through one raw buffer descriptor and
 // drop stores through an offset of 2^31 past it: they need a state below 2^31 bytes.
 inline bool tb2_fits(const Geo& G, size_t elem_bytes) {
@@ -56,6 +62,13 @@ void prepare_tb2();
 // Whether two steps per launch are faster than one for this grid and these types
 template <typename S, typename R>
 bool tb2_pays(const Geo& G, bool per_node_medium);
+// Whether kTileSteps steps per launch in LDS are faster than one for this grid and these types
+template <typename S, typename R>
+bool tile_pays(const Geo& G, bool per_node_medium);
+// kTileSteps steps of the pull layout from src to dst, each tile of the grid advanced in LDS
+template <typename S, typename R>
+hipError_t launch_tile_step(const void* src, void* dst, const void* med, const Geo& G,
+                            const Phys<R>& P, hipStream_t s);
 // Rows per segment and work-groups per launch of the two-step kernel
 template <typename S, typename R>
 void tb2_shape(const Geo& G, bool per_node_medium, int* rows, int* nwg);

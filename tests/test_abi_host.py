@@ -172,11 +172,21 @@ def test_aa_layout_halves_the_state_memory(lbm):
 def test_aa_layout_limits(lbm):
     assert status_of(lbm, layout=3) == -1                          # LBM_E_INVAL
     assert status_of(lbm, steps_per_launch=3) == -1
+    assert status_of(lbm, steps_per_launch=4) == 0                 # tiles in LDS
+    assert status_of(lbm, steps_per_launch=5) == -1
     assert status_of(lbm, layout=1, checkpoint_every=10) == -6     # LBM_E_UNSUPPORTED: no tape
     from paper_1308_2071_amd import _abi
     p = (_abi.LbmParams * 1)(lbm.make_params(nx=16, ny=16, layout="aa"))
     n = C.c_size_t()
     assert _abi.library().lbm_batch_workspace_size(1, p, C.byref(n)) == -6
+
+
+def test_a_batch_has_no_tile_form(lbm):
+    from paper_1308_2071_amd import _abi
+    p = (_abi.LbmParams * 2)(lbm.make_params(nx=32, ny=32, steps_per_launch=4),
+                             lbm.make_params(nx=32, ny=32))
+    n = C.c_size_t()
+    assert _abi.library().lbm_batch_workspace_size(2, p, C.byref(n)) == -6   # UNSUPPORTED
 
 
 def test_two_steps_per_launch_need_a_state_below_2_gib(lbm):
