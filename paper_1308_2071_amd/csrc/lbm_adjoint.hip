@@ -7,7 +7,8 @@
 // previous state, and the map x -> (i, x - e_i) is a bijection; a wall node reads nothing of its
 // own slots but the slots of its inward neighbour x_f.  So the thread of node x writes the
 // adjoint of exactly its own slots: its own collision's contribution plus the contributions of
-// every wall node whose inward neighbour is x.  Wall threads write zeros to their own slots.
+// every wall node whose inward neighbour is x, which the wall nodes' threads hand over through
+// LDS.  Wall threads write zeros to their own slots.
 #include "lbm_device.hpp"
 #include "lbm_internal.hpp"
 
@@ -178,17 +179,14 @@ __device__ __forceinline__ void macros_vjp(const R f[9], const R g[5], R phi, R 
     for (int i = 0; i < 5; ++i) ag[i] += lth;
 }
 
-// Reverse of nee_wall(): adjoints lfb, lgb of the rebuilt wall populations and ltheta_b of the
-// wall temperature flow back into the neighbour's populations (af, ag) and macroscopics (A).
+// Reverse of nee_wall() with respect to the neighbour's macroscopics: given the adjoints lfb,
+// lgb of the rebuilt wall populations, adds to A the adjoints of the neighbour's ux, uy, 1/phi
+// and theta.  The neighbour's pulled populations receive lfb and lgb unchanged.  Returns
+// sum_i wt_i lgb_i, the adjoint of the wall temperature theta_b through the rebuilt g.
 template <typename R>
-__device__ __forceinline__ void nee_vjp(const Mac<R>& mf, const Med<R>& mdf, const Phys<R>& P,
-                                        const R lfb[9], const R lgb[5], R af[9], R ag[5],
-                                        MacAdj<R>& A) {
+__device__ __forceinline__ R nee_vjp(const Mac<R>& mf, const Med<R>& mdf, const Phys<R>& P,
+                                     const R lfb[9], const R lgb[5], MacAdj<R>& A) {
     const R ux = mf.ux, uy = mf.uy, ip = mdf.inv_phi, r0 = P.rho0;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) af[i] += lfb[i];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) ag[i] += lgb[i];
     // f_b,i = f_f,i - rho0 s_i(u; phi): s_i = w_i [3 e.u + 4.5 (e.u)^2 ip - 1.5 uu ip]
     const R ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
     const R ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
@@ -206,7 +204,7 @@ __device__ __forceinline__ void nee_vjp(const Mac<R>& mf, const Med<R>& mdf, con
     }
     // g_b,i = g_f,i + wt_i (theta_b - theta_f) - wt1 T_f u_coef (e_i . u)   (i >= 1)
     const R sw = P.wt0 * lgb[0] + P.wt1 * ((lgb[1] + lgb[2]) + (lgb[3] + lgb[4]));
-    A.theta -= sw;                           // via theta_f (the wall's own share is returned)
+    A.theta -= sw;                           // via theta_f
     const R k = P.wt1 * P.u_coef;
     const R Tf = P.T0 + mf.theta;
     const R dx = lgb[1] - lgb[3], dy = lgb[2] - lgb[4];
@@ -216,7 +214,7 @@ __device__ __forceinline__ void nee_vjp(const Mac<R>& mf, const Med<R>& mdf, con
     A.ux += lux;
     A.uy += luy;
     A.ip += lip;
-    // the caller adds sw to the wall temperature's adjoint
+    return sw;
 }
 
 template <typename R>
@@ -225,46 +223,55 @@ __device__ __forceinline__ bool on_wall(const Geo& G, int x, int y) {
            (G.wallN && y == G.ny - 1);
 }
 
-// Adjoint of the wall node (xb, yb)'s collision (u = 0, P_b = P_f, theta_b, F_b = phi_b G_b).
-// Returns the adjoints of its rebuilt populations in lfb, lgb, and of theta_b and phi_b.
-template <typename R>
-__device__ __forceinline__ void wall_collide_vjp(const R fb[9], const R gb[5], R theta_b, R P_b,
-                                                 R phi_b, const Phys<R>& P, const R lout[14],
-                                                 R lfb[9], R lgb[5], R& ltheta_b, R& lphi_b,
-                                                 R& lP_b) {
-    Mac<R> mb;
-    mb.theta = theta_b;
-    mb.ux = R(0);
-    mb.uy = R(0);
-    mb.P = P_b;
-    const R Gy = P.ay + P.gbeta * theta_b;
-    mb.Fx = phi_b * P.ax;
-    mb.Fy = phi_b * Gy;
-    Med<R> mdb{phi_b, R(1) / phi_b, R(0), R(0)};
-    MacAdj<R> A{};
-#pragma unroll
-    for (int i = 0; i < 9; ++i) lfb[i] = R(0);
-#pragma unroll
-    for (int i = 0; i < 5; ++i) lgb[i] = R(0);
-    collide_vjp<R>(fb, gb, mb, mdb, P, lout, lout + 9, lfb, lgb, A);
-    lphi_b = P.ax * A.Fx + Gy * A.Fy;
-    ltheta_b = A.theta + phi_b * P.gbeta * A.Fy;
-    lP_b = A.P;
+// Work-group tiles of the backward step: kAdjTX x kAdjTY nodes, one work-item each, one
+// wavefront per row.  Every wall node shares its tile with its inward neighbour: where the
+// last tile along a walled axis would be one node wide, it starts one node earlier and the tile
+// before it ends there (a walled axis has at least five nodes).
+constexpr int kAdjTX = 64, kAdjTY = 4, kAdjThreads = kAdjTX * kAdjTY;
+// What a wall node hands its inward neighbour: the adjoints of the neighbour's 14 pulled
+// populations and of its ux, uy, 1/phi, theta and P.
+constexpr int kHandoff = 19;
+
+struct AdjTiles {
+    int nx_tiles, ny_tiles;
+    int last_x0, last_y0;   // first column and first row of the last tile along x and y
+};
+
+// Nodes [a, b) of tile t of T along an axis of n nodes.
+__device__ __forceinline__ void adj_span(int t, int T, int side, int last0, int n, int& a,
+                                         int& b) {
+    a = t == T - 1 ? last0 : t * side;
+    b = t == T - 1 ? n : min((t + 1) * side, last0);
 }
 
 // One backward step.  state: the forward state X^n (post-collision populations entering step
 // n); lam_in: adjoint of X^{n+1}; lam_out: adjoint of X^n (written); gphi, gK: FP64 gradient
 // planes [ny][pitch] accumulated in place.  S: storage type of state, adjoint and medium;
 // R: arithmetic type.
+//
+// A fluid node's work-item reverses its own collision and macroscopics.  A wall node's
+// work-item runs the same gather, macroscopics and collision VJP on the wall node's own
+// reconstructed state (so both kinds of node stay in step), adds its dJ/dphi (through
+// F_b = phi_b G_b), writes zeros to its own slots (the forward step never reads them) and hands
+// its inward neighbour, through LDS, what flows back through the reconstruction.  After one
+// barrier the neighbour adds up to three hand-offs (two sides and their corner) in a fixed
+// order before reversing its own macroscopics.
 template <typename S, typename R, bool PN>
-__global__ __launch_bounds__(256) void adjoint_step_kernel(
+__global__ __launch_bounds__(kAdjThreads) void adjoint_step_kernel(
     const S* __restrict__ state, const S* __restrict__ lam_in, S* __restrict__ lam_out,
     const S* __restrict__ med, double* __restrict__ gphi, double* __restrict__ gK, Geo G,
-    Phys<R> P, int tiles_x) {
-    const int t = blockIdx.x;
-    const int y = t / tiles_x;
-    const int x = (t - y * tiles_x) * 256 + threadIdx.x;
-    if (x >= G.nx) return;
+    Phys<R> P, AdjTiles T) {
+    __shared__ R handoff[kHandoff][kAdjThreads];
+    const int tx = blockIdx.x % T.nx_tiles, ty = blockIdx.x / T.nx_tiles;
+    int x0, x1, y0, y1;
+    adj_span(tx, T.nx_tiles, kAdjTX, T.last_x0, G.nx, x0, x1);
+    adj_span(ty, T.ny_tiles, kAdjTY, T.last_y0, G.ny, y0, y1);
+    const int me = threadIdx.x;
+    const int x = x0 + me % kAdjTX, y = y0 + me / kAdjTX;
+    const bool active = x < x1 && y < y1;
+    const bool onW = G.wallW && x == 0, onE = G.wallE && x == G.nx - 1;
+    const bool onS = G.wallS && y == 0, onN = G.wallN && y == G.ny - 1;
+    const bool wall = onW || onE || onS || onN;
     const int o = y * G.pitch + x;
     const int xm = (x == 0) ? G.nx - 1 : x - 1;
     const int xp = (x == G.nx - 1) ? 0 : x + 1;
@@ -274,102 +281,121 @@ __global__ __launch_bounds__(256) void adjoint_step_kernel(
     // side of the domain
     const int sx[9] = {x, xm, x, xp, x, xm, xp, xp, xm};
     const int sy[9] = {y, y, ym, y, yp, ym, ym, yp, yp};
-    const bool okx_m = !(G.wallW && x == 0), okx_p = !(G.wallE && x == G.nx - 1);
-    const bool oky_m = !(G.wallS && y == 0), oky_p = !(G.wallN && y == G.ny - 1);
-    const bool ok[9] = {true, okx_m, oky_m, okx_p, oky_p, okx_m && oky_m, okx_p && oky_m,
-                        okx_p && oky_p, okx_m && oky_p};
 
-    if (on_wall<R>(G, x, y)) {
-        // own slots are not read in the forward step
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-            if (ok[i]) lam_out[i * G.plane + sy[i] * G.pitch + sx[i]] = S(0);
-#pragma unroll
-        for (int i = 0; i < 5; ++i)
-            if (ok[i]) lam_out[(9 + i) * G.plane + sy[i] * G.pitch + sx[i]] = S(0);
-        // d/dphi_b through F_b = phi_b G_b
-        R f[9], g[5];
-        Mac<R> m;
-        Med<R> md;
-        node_state<R, PN, S>(state, med, G, P, x, y, f, g, m, md);
+    R f[9], g[5], af[9], ag[5], phi = 0, K = 0;
+    Med<R> md{};
+    MacAdj<R> A{};
+    // the gradient planes are read before the barrier, which global loads do not cross, so
+    // that their latency hides behind the step's arithmetic
+    double gphi0 = 0, gK0 = 0;
+    if (active) {
+        gphi0 = gphi[o];
+        if (!wall) gK0 = gK[o];
+        // the node whose pulled populations this node's state is built from: itself, or its
+        // inward neighbour (the diagonal one at a corner)
+        const int px = x + (onW ? 1 : 0) - (onE ? 1 : 0);
+        const int py = y + (onS ? 1 : 0) - (onN ? 1 : 0);
+        pull<R, S>(state, G, px, py, f, g);
+        if constexpr (PN) {
+            const int op = py * G.pitch + px;
+            phi = R(med[op]);
+            K = R(med[G.plane + op]);
+            md = medium_from<R>(phi, K, P);
+        } else {
+            phi = P.phi;
+            K = P.c_lin > R(0) ? phi * P.nu / P.c_lin : R(INFINITY);
+            md = Med<R>{P.phi, P.inv_phi, P.c_lin, P.c_nl};
+        }
+        const Mac<R> m = fluid_macros<R>(f, g, md, P);
         R lout[14];
 #pragma unroll
         for (int i = 0; i < 14; ++i) lout[i] = R(lam_in[i * G.plane + o]);
-        R lfb[9], lgb[5], lth, lphib, lPb;
-        wall_collide_vjp<R>(f, g, m.theta, m.P, md.phi, P, lout, lfb, lgb, lth, lphib, lPb);
-        gphi[o] += double(lphib);
-        return;
-    }
-
-    // fluid node: forward recompute
-    R f[9], g[5];
-    pull<R, S>(state, G, x, y, f, g);
-    R phi, K;
-    if constexpr (PN) {
-        phi = R(med[o]);
-        K = R(med[G.plane + o]);
-    } else {
-        phi = P.phi;
-        K = P.c_lin > R(0) ? phi * P.nu / P.c_lin : R(INFINITY);
-    }
-    const Med<R> md = medium_from<R>(phi, K, P);
-    Med<R> mdu = md;
-    if constexpr (!PN) mdu = Med<R>{P.phi, P.inv_phi, P.c_lin, P.c_nl};
-    const Mac<R> m = fluid_macros<R>(f, g, mdu, P);
-    R lout[14];
+        Mac<R> mc = m;
+        Med<R> mdc = md;
+        R theta_b = 0, phi_b = 0;
+        if (wall) {
+            // the wall node's state: rebuilt from its neighbour's, at rest, with its own phi
+            theta_b = wall_theta<R>(onW, onE, onS, onN, m.theta, P);
+            nee_wall<R>(f, g, m, md, theta_b, P);
+            phi_b = PN ? R(med[o]) : P.phi;
+            mc.theta = theta_b;
+            mc.ux = R(0);
+            mc.uy = R(0);
+            mc.Fx = phi_b * P.ax;
+            mc.Fy = phi_b * (P.ay + P.gbeta * theta_b);
+            mdc = Med<R>{phi_b, R(1) / phi_b, R(0), R(0)};
+        }
 #pragma unroll
-    for (int i = 0; i < 14; ++i) lout[i] = R(lam_in[i * G.plane + o]);
-    R af[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, ag[5] = {0, 0, 0, 0, 0};
-    MacAdj<R> A{};
-    collide_vjp<R>(f, g, m, mdu, P, lout, lout + 9, af, ag, A);
-    R lphi = 0, lK = 0;
+        for (int i = 0; i < 9; ++i) af[i] = R(0);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) ag[i] = R(0);
+        collide_vjp<R>(f, g, mc, mdc, P, lout, lout + 9, af, ag, A);
+        if (wall) {
+            // at rest the collision depends on 1/phi_b only through terms in u = 0, so phi_b
+            // acts through F_b alone; theta_b through the collision, F_b and the rebuilt g
+            const R Gy = P.ay + P.gbeta * theta_b;
+            const R lphib = P.ax * A.Fx + Gy * A.Fy;
+            const R lthb = A.theta + phi_b * P.gbeta * A.Fy;
+            MacAdj<R> H{};
+            const R sw = nee_vjp<R>(m, md, P, af, ag, H);
+            const bool adiabatic = !((onW && P.iso[0]) || (onE && P.iso[1]) ||
+                                     (onS && P.iso[2]) || (onN && P.iso[3]));
+            if (adiabatic) H.theta += lthb + sw;    // theta_b = theta_f on an adiabatic side
+#pragma unroll
+            for (int i = 0; i < 9; ++i) handoff[i][me] = af[i];
+#pragma unroll
+            for (int i = 0; i < 5; ++i) handoff[9 + i][me] = ag[i];
+            handoff[14][me] = H.ux;
+            handoff[15][me] = H.uy;
+            handoff[16][me] = H.ip;
+            handoff[17][me] = H.theta;
+            handoff[18][me] = A.P;
+            const bool okx_m = !onW, okx_p = !onE, oky_m = !onS, oky_p = !onN;
+            const bool ok[9] = {true, okx_m, oky_m, okx_p, oky_p, okx_m && oky_m,
+                                okx_p && oky_m, okx_p && oky_p, okx_m && oky_p};
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                if (ok[i]) lam_out[i * G.plane + sy[i] * G.pitch + sx[i]] = S(0);
+#pragma unroll
+            for (int i = 0; i < 5; ++i)
+                if (ok[i]) lam_out[(9 + i) * G.plane + sy[i] * G.pitch + sx[i]] = S(0);
+            gphi[o] = gphi0 + double(lphib);
+        }
+    }
+    __syncthreads();
+    if (!active || wall) return;
 
-    // wall nodes whose inward neighbour is this node
+    // hand-offs of the wall nodes whose inward neighbour this node is, in a fixed order
     const bool nearW = G.wallW && x == 1, nearE = G.wallE && x == G.nx - 2;
     const bool nearS = G.wallS && y == 1, nearN = G.wallN && y == G.ny - 2;
     if (nearW || nearE || nearS || nearN) {
+        const bool has[8] = {nearW,          nearE,          nearS,          nearN,
+                             nearW && nearS, nearE && nearS, nearW && nearN, nearE && nearN};
         const int dxs[8] = {-1, 1, 0, 0, -1, 1, -1, 1};
         const int dys[8] = {0, 0, -1, 1, -1, -1, 1, 1};
+#pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const int xb = x + dxs[k], yb = y + dys[k];
-            if (xb < 0 || xb >= G.nx || yb < 0 || yb >= G.ny) continue;
-            const bool bW = G.wallW && xb == 0, bE = G.wallE && xb == G.nx - 1;
-            const bool bS = G.wallS && yb == 0, bN = G.wallN && yb == G.ny - 1;
-            if (!(bW || bE || bS || bN)) continue;
-            const int xf = xb + (bW ? 1 : 0) - (bE ? 1 : 0);
-            const int yf = yb + (bS ? 1 : 0) - (bN ? 1 : 0);
-            if (xf != x || yf != y) continue;
-            // forward of the wall node
-            const R theta_b = wall_theta<R>(bW, bE, bS, bN, m.theta, P);
-            const bool adiabatic = !((bW && P.iso[0]) || (bE && P.iso[1]) ||
-                                     (bS && P.iso[2]) || (bN && P.iso[3]));
-            R fb[9], gb[5];
+            if (!has[k]) continue;
+            const int j = me + dys[k] * kAdjTX + dxs[k];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) fb[i] = f[i];
+            for (int i = 0; i < 9; ++i) af[i] += handoff[i][j];
 #pragma unroll
-            for (int i = 0; i < 5; ++i) gb[i] = g[i];
-            nee_wall<R>(fb, gb, m, mdu, theta_b, P);
-            const int ob = yb * G.pitch + xb;
-            R lb[14];
-#pragma unroll
-            for (int i = 0; i < 14; ++i) lb[i] = R(lam_in[i * G.plane + ob]);
-            const R phi_b = PN ? R(med[ob]) : P.phi;
-            R lfb[9], lgb[5], lthb, lphib, lPb;
-            wall_collide_vjp<R>(fb, gb, theta_b, m.P, phi_b, P, lb, lfb, lgb, lthb, lphib, lPb);
-            (void)lphib;  // accumulated by the wall node's own thread
-            nee_vjp<R>(m, mdu, P, lfb, lgb, af, ag, A);
-            lthb += P.wt0 * lgb[0] + P.wt1 * ((lgb[1] + lgb[2]) + (lgb[3] + lgb[4]));
-            if (adiabatic) A.theta += lthb;
-            A.P += lPb;
+            for (int i = 0; i < 5; ++i) ag[i] += handoff[9 + i][j];
+            A.ux += handoff[14][j];
+            A.uy += handoff[15][j];
+            A.ip += handoff[16][j];
+            A.theta += handoff[17][j];
+            A.P += handoff[18][j];
         }
     }
-    macros_vjp<R>(f, g, phi, K, mdu, P, A, af, ag, lphi, lK);
+    R lphi = 0, lK = 0;
+    macros_vjp<R>(f, g, phi, K, md, P, A, af, ag, lphi, lK);
 #pragma unroll
     for (int i = 0; i < 9; ++i) lam_out[i * G.plane + sy[i] * G.pitch + sx[i]] = S(af[i]);
 #pragma unroll
     for (int i = 0; i < 5; ++i) lam_out[(9 + i) * G.plane + sy[i] * G.pitch + sx[i]] = S(ag[i]);
-    gphi[o] += double(lphi);
-    gK[o] += double(lK);
+    gphi[o] = gphi0 + double(lphi);
+    gK[o] = gK0 + double(lK);
 }
 
 // Seed: adjoint of X^N for J = Nu_hot(T at time N).  T(x) = T0 + sum_i g_i(x - e_i) at a fluid
@@ -447,16 +473,20 @@ template <typename S, typename R>
 hipError_t launch_adjoint_step(const void* state, const void* lam_in, void* lam_out,
                                const void* med, double* gphi, double* gK, const Geo& G,
                                const Phys<R>& P, hipStream_t s) {
-    const int tiles_x = (G.nx + 255) / 256;
-    const int nwg = tiles_x * G.ny;
+    AdjTiles T;
+    T.nx_tiles = (G.nx + kAdjTX - 1) / kAdjTX;
+    T.ny_tiles = (G.ny + kAdjTY - 1) / kAdjTY;
+    T.last_x0 = (T.nx_tiles - 1) * kAdjTX;
+    T.last_y0 = (T.ny_tiles - 1) * kAdjTY;
+    if (G.wallE && G.nx - T.last_x0 == 1) T.last_x0 = G.nx - 2;
+    if (G.wallN && G.ny - T.last_y0 == 1) T.last_y0 = G.ny - 2;
+    const int nwg = T.nx_tiles * T.ny_tiles;
     if (med)
-        adjoint_step_kernel<S, R, true><<<nwg, 256, 0, s>>>((const S*)state, (const S*)lam_in,
-                                                            (S*)lam_out, (const S*)med, gphi, gK,
-                                                            G, P, tiles_x);
+        adjoint_step_kernel<S, R, true><<<nwg, kAdjThreads, 0, s>>>(
+            (const S*)state, (const S*)lam_in, (S*)lam_out, (const S*)med, gphi, gK, G, P, T);
     else
-        adjoint_step_kernel<S, R, false><<<nwg, 256, 0, s>>>((const S*)state, (const S*)lam_in,
-                                                             (S*)lam_out, nullptr, gphi, gK, G,
-                                                             P, tiles_x);
+        adjoint_step_kernel<S, R, false><<<nwg, kAdjThreads, 0, s>>>(
+            (const S*)state, (const S*)lam_in, (S*)lam_out, nullptr, gphi, gK, G, P, T);
     return hipGetLastError();
 }
 

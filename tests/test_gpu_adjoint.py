@@ -47,6 +47,9 @@ CASES = {
     "channel": (dict(bc=(ISO, ISO, PER, PER), T_wall=(1.0, 0.0, 0.0, 0.0),
                      ext_accel=(0.0, 1e-4)), (9, 8)),
     "ragged": (dict(bc=(ISO, ISO, ADIA, ADIA), T_wall=(1.0, 0.0, 0.0, 0.0)), (300, 7)),
+    # 65 columns and 9 rows: the backward kernel's last tile along each walled axis would be one
+    # node wide, so it starts one node earlier to keep the wall nodes with their neighbours
+    "shifted_tiles": (dict(bc=(ISO, ADIA, ISO, ADIA), T_wall=(1.0, 0.0, 0.5, 0.0)), (65, 9)),
 }
 
 
