@@ -2,7 +2,9 @@
 halo of four nodes) against one step per launch: bitwise equal fields and Nusselt numbers for
 every boundary setting, grid shapes from the smallest allowed to ragged ones whose last tile is
 one node thick at a wall, all precisions, per-node and uniform media, step counts that are not
-multiples of four (the remainder runs as single steps) and graph-replayed runs.
+multiples of four (the remainder runs as single steps) and graph-replayed runs.  With a tape the
+tiles run between checkpoints, and the gradients equal those of a one-step-per-launch forward
+bitwise.
 """
 import pytest
 import torch
@@ -99,5 +101,48 @@ def test_tiles_between_checkpoints_keep_the_tape_exact(C):
     ga, gb = a.grad(), b.grad()
     for x, y in zip(ga, gb):
         assert torch.equal(x, y), f"C={C}"
+    a.close()
+    b.close()
+
+
+ADJ_BCS = ("side_heated", "mixed", "all_iso", "channel_y")
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp64", "fp32_f64"])
+@pytest.mark.parametrize("shape", [(5, 5), (7, 6), (21, 19), (37, 21), (19, 37), (64, 33)])
+@pytest.mark.parametrize("bc", ADJ_BCS)
+def test_gradients_equal_with_and_without_forward_tiles(bc, shape, dtype):
+    """Gradients of J = Nu_hot after a forward pass in LDS tiles (between checkpoints) against
+    one step per launch: the tape's states, and so the gradients, are bitwise equal.  Segments of
+    7 steps leave remainders that go one step at a time; the shapes include ragged last tiles."""
+    nx, ny = shape
+    n, C = 23, 7
+    params = dict(nx=nx, ny=ny, Ra=1e5, Pr=0.71, checkpoint_every=C, **BCS[bc])
+    phi, K = workloads.random_medium(ny, nx, seed=5 * nx + ny)
+    tdt = torch.float64 if dtype == "fp64" else torch.float32
+    kw = dict(phi=torch.tensor(phi, dtype=tdt), K=torch.tensor(K, dtype=tdt), nsteps_max=n)
+    a = Cavity(dict(params, dtype=dtype, steps_per_launch=1), **kw)
+    b = Cavity(dict(params, dtype=dtype, steps_per_launch=4), **kw)
+    a.step(n)
+    b.step(n)
+    assert_same(a, b, f"{bc} {shape} {dtype}")
+    ga, gb = a.grad(), b.grad()
+    for x, y in zip(ga, gb):
+        assert torch.isfinite(x).all()
+        assert torch.equal(x, y), f"{bc} {shape} {dtype}"
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+def test_gradients_with_forward_tiles_uniform_medium_and_heat_source(dtype):
+    params = dict(nx=45, ny=38, Ra=1e5, Ra_I=1e5, Pr=0.7, Da=1e-2, checkpoint_every=10)
+    a = Cavity(dict(params, dtype=dtype, steps_per_launch=1), phi_uniform=0.4, nsteps_max=30)
+    b = Cavity(dict(params, dtype=dtype, steps_per_launch=4), phi_uniform=0.4, nsteps_max=30)
+    a.step(30)
+    b.step(30)
+    for x, y in zip(a.grad(), b.grad()):
+        assert torch.isfinite(x).all() and x.abs().max() > 0
+        assert torch.equal(x, y), dtype
     a.close()
     b.close()
