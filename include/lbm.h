@@ -104,10 +104,10 @@ typedef struct {
                              /* (the intermediate step kept in registers) where that is      */
                              /* faster (large grids, storage type = arithmetic type), four   */
                              /* (16 x 16 tiles advanced in LDS) where that is (small grids), */
-                             /* else one.  1: one.  2: two, wherever the pull layout without */
-                             /* a tape allows; it needs a state (14 planes) below 2 GiB and  */
-                             /* gives LBM_E_UNSUPPORTED beyond.  4: four (with a tape, only  */
-                             /* between checkpoints).  The AA layout steps one at a time.    */
+                             /* else one.  1: one.  2: two; it needs a state (14 planes)     */
+                             /* below 2 GiB and gives LBM_E_UNSUPPORTED beyond.  4: four.    */
+                             /* With a tape, launches of two or four steps run only between  */
+                             /* checkpoints.  The AA layout steps one at a time.             */
                              /* Results are bitwise the same in every case.                  */
 } lbm_params;
 

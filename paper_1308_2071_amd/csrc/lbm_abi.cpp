@@ -408,16 +408,14 @@ hipError_t advance_k(lbm_ctx* c, int k, int from, hipStream_t s) {
 
 // Time steps per launch of the time loop: one with the AA layout; steps_per_launch when it
 // asks for 1, 2 or kTileSteps; by default two (the two-step kernel) where that is measured to
-// pay, else kTileSteps (the tiles in LDS) where that is, else one.  With a tape the two-step
-// kernel is not used, and the tiles only between checkpoints (lbm_step).
+// pay, else kTileSteps (the tiles in LDS) where that is, else one.  With a tape, launches of
+// several steps run only between checkpoints (lbm_step).
 int launch_steps(const lbm_ctx* c) {
     if (c->p.layout != LBM_LAYOUT_PULL) return 1;
-    const bool tape = c->p.checkpoint_every != 0;
-    if (c->p.steps_per_launch != 0)
-        return tape && c->p.steps_per_launch == 2 ? 1 : c->p.steps_per_launch;
+    if (c->p.steps_per_launch != 0) return c->p.steps_per_launch;
     return with_types(c->p.dtype, [&](auto st, auto rt) {
         LBM_TYPES(st, rt)
-        if (!tape && tb2_pays<S, R>(c->G, c->med)) return 2;
+        if (tb2_pays<S, R>(c->G, c->med)) return 2;
         return tile_pays<S, R>(c->G, c->med) ? kTileSteps : 1;
     });
 }

@@ -7,7 +7,7 @@ oracle parity tests run on the fused path as well, since it is the default.
 import pytest
 import torch
 
-from paper_1308_2071_amd import Cavity, workloads
+from paper_1308_2071_amd import Cavity, lbm_step_shape, workloads
 
 pytestmark = pytest.mark.gpu
 
@@ -71,3 +71,47 @@ def test_fused_graph_replay_uniform_medium_and_heat_source(dtype):
     assert_same(a, b, "257 steps")
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+@pytest.mark.parametrize("C", [3, 4, 7])
+@pytest.mark.parametrize("shape", [(40, 30), (70, 33), (130, 21)])
+def test_two_steps_between_checkpoints_keep_the_tape_exact(shape, C, dtype):
+    """With a tape, two-step launches run only between checkpoints (an odd interval leaves one
+    single step per segment): fields, Nusselt numbers and the gradients of J = Nu_hot equal those
+    of one step per launch bitwise."""
+    nx, ny = shape
+    n = 23
+    params = dict(nx=nx, ny=ny, Ra=1e5, Pr=0.71, dtype=dtype, checkpoint_every=C,
+                  bc=(0, 0, 1, 1), T_wall=(1.0, 0.0, 0.0, 0.0))
+    phi, K = workloads.random_medium(ny, nx, seed=3 * nx + ny + C)
+    tdt = torch.float64 if dtype == "fp64" else torch.float32
+    kw = dict(phi=torch.tensor(phi, dtype=tdt), K=torch.tensor(K, dtype=tdt), nsteps_max=n)
+    a = Cavity(dict(params, steps_per_launch=1), **kw)
+    b = Cavity(dict(params, steps_per_launch=2), **kw)
+    assert lbm_step_shape(b.ctx)[0] == 2
+    a.step(n)
+    b.step(n)
+    oa, ob = a.observables(), b.observables()
+    for k in ("ux", "uy", "p", "T"):
+        assert torch.equal(oa[k], ob[k]), k
+    assert oa["nu_hot"] == ob["nu_hot"]
+    for x, y in zip(a.grad(), b.grad()):
+        assert torch.isfinite(x).all()
+        assert torch.equal(x, y)
+    a.close()
+    b.close()
+
+
+def test_a_tape_keeps_the_default_steps_per_launch():
+    """The default form of the time loop (two steps per launch on this grid) is the same with and
+    without a tape."""
+    params = dict(nx=1024, ny=1024, dtype="fp32", Ra=1e5, Pr=0.71)
+    phi, K = workloads.random_medium(1024, 1024, seed=5)
+    kw = dict(phi=torch.tensor(phi, dtype=torch.float32), K=torch.tensor(K, dtype=torch.float32))
+    plain = Cavity(params, **kw)
+    taped = Cavity(dict(params, checkpoint_every=2), nsteps_max=4, **kw)
+    assert lbm_step_shape(plain.ctx)[0] == 2
+    assert lbm_step_shape(taped.ctx)[0] == 2
+    plain.close()
+    taped.close()
