@@ -162,8 +162,9 @@ lbm_status validate(const lbm_params& p) {
         return fail(LBM_E_INVAL, "steps_per_launch = %d is not 0, 1, 2 or %d", p.steps_per_launch,
                     kTileSteps);
     if (p.steps_per_launch == 2 &&
-        plane_elems(pitch, p.ny) * kPlanes * (long long)storage_bytes(p.dtype) >= (1LL << 31))
-        return fail(LBM_E_UNSUPPORTED, "two steps per launch need a state below 2 GiB");
+        plane_elems(pitch, p.ny) * (kPlanes / 2) * (long long)storage_bytes(p.dtype) >= (1LL << 31))
+        return fail(LBM_E_UNSUPPORTED,
+                    "two steps per launch need each half of the state (7 planes) below 2 GiB");
     if (p.layout == LBM_LAYOUT_AA && p.checkpoint_every > 0)
         return fail(LBM_E_UNSUPPORTED, "the AA layout has no adjoint tape");
     const Derived d = derive(p);
@@ -511,7 +512,7 @@ lbm_status batch_layout(int32_t n, const lbm_params* p, BatchLayout* L) {
         if (i == 0 && p[0].steps_per_launch == kTileSteps)
             return fail(LBM_E_UNSUPPORTED, "a batch steps one or two steps per launch");
         const Geo G = make_geo(p[i]);
-        if (p[0].steps_per_launch == 2 && !tb2_fits(G, storage_bytes(dt)))
+        if (p[0].steps_per_launch == 2 && tb2_descs(G, storage_bytes(dt)) != 1)
             return fail(LBM_E_UNSUPPORTED,
                         "cavity %d: two steps per launch need a state below 2 GiB", i);
         L->off.push_back(elems);
@@ -842,7 +843,8 @@ lbm_status batch_tune(lbm_ctx* c, const char* path) {
         if (st != LBM_OK) break;
     }
     bool fit = true;  // the two-step kernel needs each cavity's state below 2 GiB
-    for (int i = 0; i < c->ncav; ++i) fit = fit && tb2_fits(c->bG[i], storage_bytes(c->p.dtype));
+    for (int i = 0; i < c->ncav; ++i)
+        fit = fit && tb2_descs(c->bG[i], storage_bytes(c->p.dtype)) == 1;
     if (st == LBM_OK && spl != 1 && fit) {
         for (int tr : tb_rows) {
             for (int tw : tb_waves) {

@@ -44,11 +44,18 @@ constexpr int kTileSide = 16;
 constexpr int kTileSteps = 4;
 constexpr int kTileThreads = 640;   // one work-item per node of the largest region (25^2)
 
-// The two-step kernels address a state (the 14 planes) through one raw buffer descriptor and
-// drop stores through an offset of 2^31 past it: they need a state below 2^31 bytes.
-inline bool tb2_fits(const Geo& G, size_t elem_bytes) {
-    return (unsigned long long)kPlanes * (unsigned long long)G.plane * elem_bytes < (1ull << 31);
+// The two-step kernels address a state (the 14 planes) through raw buffer descriptors and drop
+// stores through an offset of 2^31 past them, so a descriptor covers less than 2^31 bytes: one
+// descriptor for a state below 2^31 bytes, two (planes 0-6 and 7-13) for a state whose halves
+// are.  tb2_descs gives the number of descriptors a state needs, 0 if even its halves are too
+// large.  The batched two-step kernel uses one descriptor per cavity.
+inline int tb2_descs(const Geo& G, size_t elem_bytes) {
+    const unsigned long long pb = (unsigned long long)G.plane * elem_bytes;
+    if (kPlanes * pb < (1ull << 31)) return 1;
+    if (kPlanes / 2 * pb < (1ull << 31)) return 2;
+    return 0;
 }
+inline bool tb2_fits(const Geo& G, size_t elem_bytes) { return tb2_descs(G, elem_bytes) > 0; }
 
 // Launchers take S, the storage type of populations and medium planes, and R, the arithmetic
 // type; instantiated for (float, float), (double, double) and (float, double).

@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kTileX) void aa_step_kernel(S* __restrict__ buf,
     aa_store<S, R, L>(buf, G, x, y, f, g);
 }
 
-template <typename S, typename R, bool PN>
+template <typename S, typename R, bool PN, int NDESC>
 __global__ __launch_bounds__(64 * kTbWaves, (tb_min_waves<S, R>())) void tb2_step_kernel(const S* __restrict__ src,
                                                                  S* __restrict__ dst,
                                                                  const S* __restrict__ med,
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(64 * kTbWaves, (tb_min_waves<S, R>())) void tb2_ste
     const int wg = tb_logical_group(chunk);
     const int ngrp = (nstrips + kTbWaves - 1) / kTbWaves;
     const int strip = (wg % ngrp) * kTbWaves + (threadIdx.x >> 6), seg = wg / ngrp;
-    tb2_segment<S, R, PN>(src, dst, med, G, P, strip, strip < nstrips, seg, rows);
+    tb2_segment<S, R, PN, NDESC>(src, dst, med, G, P, strip, strip < nstrips, seg, rows);
 }
 
 // Maximum and minimum that propagate a NaN (fmax and fmin would drop it), so that a
@@ -326,7 +326,7 @@ int tb_resident_groups() {
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
                 hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tb2_step_kernel<S, R, PN>,
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tb2_step_kernel<S, R, PN, 1>,
                                                          64 * kTbWaves, 0) != hipSuccess)
             return 0;
         return cus * per_cu;
@@ -371,7 +371,7 @@ void prepare_tb2() {
 // On small grids the few long row loops are latency-bound.  With equal types the kernel fuses
 // when its work-groups at 16-row segments number at least a quarter of the resident set, with
 // FP64 arithmetic on FP32 storage when they number eight times the resident set; and only for
-// a state below 2 GiB, which one buffer descriptor addresses.
+// a state whose halves (7 planes) are below 2 GiB, which two buffer descriptors address.
 template <typename S, typename R>
 bool tb2_pays(const Geo& G, bool per_node_medium) {
     if (!tb2_fits(G, sizeof(S))) return false;
@@ -393,17 +393,24 @@ void tb2_shape(const Geo& G, bool per_node_medium, int* rows, int* nwg) {
 template <typename S, typename R>
 hipError_t launch_tb2_step(const void* src, void* dst, const void* med, const Geo& G,
                            const Phys<R>& P, hipStream_t s) {
-    if (!tb2_fits(G, sizeof(S))) return hipErrorInvalidValue;
+    const int ndesc = tb2_descs(G, sizeof(S));
+    if (ndesc == 0) return hipErrorInvalidValue;
     const int nstrips = (G.nx + kTbCols - 1) / kTbCols;
     int rows = 0, nwg = 0;
     tb2_shape<S, R>(G, med != nullptr, &rows, &nwg);
     // XCD chunks of one XCD's resident work-groups (the resident set over 8 XCDs)
     const int chunk = max(1, tb_resident<S, R>(med != nullptr) / 8);
-    if (med)
-        tb2_step_kernel<S, R, true><<<nwg, 64 * kTbWaves, 0, s>>>(
+    if (med && ndesc == 1)
+        tb2_step_kernel<S, R, true, 1><<<nwg, 64 * kTbWaves, 0, s>>>(
             (const S*)src, (S*)dst, (const S*)med, G, P, nstrips, rows, chunk);
+    else if (med)
+        tb2_step_kernel<S, R, true, 2><<<nwg, 64 * kTbWaves, 0, s>>>(
+            (const S*)src, (S*)dst, (const S*)med, G, P, nstrips, rows, chunk);
+    else if (ndesc == 1)
+        tb2_step_kernel<S, R, false, 1><<<nwg, 64 * kTbWaves, 0, s>>>(
+            (const S*)src, (S*)dst, nullptr, G, P, nstrips, rows, chunk);
     else
-        tb2_step_kernel<S, R, false><<<nwg, 64 * kTbWaves, 0, s>>>(
+        tb2_step_kernel<S, R, false, 2><<<nwg, 64 * kTbWaves, 0, s>>>(
             (const S*)src, (S*)dst, nullptr, G, P, nstrips, rows, chunk);
     return hipGetLastError();
 }

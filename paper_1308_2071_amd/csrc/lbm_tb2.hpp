@@ -21,8 +21,9 @@ namespace lbm {
 // The state is addressed through raw buffer descriptors: a lane's column offsets are fixed for
 // the whole segment, and a row's plane and row offsets are wave-uniform scalars, so no vector
 // instruction computes an address on the fast path and a few scalar registers replace the 64-bit
-// base of every plane.  A descriptor covers the 14 planes of one state, which must hold fewer
-// than 2^31 bytes (tb2_fits), so that an offset of 2^31 is out of range on its own.
+// base of every plane.  A descriptor covers fewer than 2^31 bytes, so that an offset of 2^31 is
+// out of range on its own: one covers the 14 planes of a state below 2^31 bytes, two (planes
+// 0-6 and 7-13) a larger one whose halves are below it (tb2_descs).
 
 // Fourth descriptor word of a raw buffer on the gfx9 family: 32-bit data format (a zero format
 // makes raw loads return zero), no stride, no swizzle.
@@ -60,6 +61,35 @@ __device__ __forceinline__ void buf_store(S v, __amdgpu_buffer_rsrc_t r, unsigne
                                               int(soff), 0);
 }
 
+// The 14 planes of a state through NDESC descriptors (1 or 2; see tb2_descs).  Plane indices
+// are constants after unrolling, so the choice of descriptor costs nothing at run time.
+template <typename S, int NDESC>
+struct TbState {
+    static_assert(NDESC == 1 || NDESC == 2, "one or two descriptors");
+    __amdgpu_buffer_rsrc_t lo, hi;
+    unsigned PB;   // bytes per plane
+    __device__ __forceinline__ TbState(const void* base, unsigned pb) : PB(pb) {
+        if constexpr (NDESC == 1) {
+            lo = hi = buf_rsrc(base, kPlanes * pb);
+        } else {
+            lo = buf_rsrc(base, kPlanes / 2 * pb);
+            hi = buf_rsrc(static_cast<const char*>(base) + size_t(kPlanes / 2) * pb,
+                          kPlanes / 2 * pb);
+        }
+    }
+    // plane p at byte offset voff (per lane) + soff (wave-uniform, within the plane)
+    __device__ __forceinline__ S load(int p, unsigned voff, unsigned soff) const {
+        if (NDESC == 1 || p < kPlanes / 2) return buf_load<S>(lo, voff, soff + unsigned(p) * PB);
+        return buf_load<S>(hi, voff, soff + unsigned(p - kPlanes / 2) * PB);
+    }
+    __device__ __forceinline__ void store(S v, int p, unsigned voff, unsigned soff) const {
+        if (NDESC == 1 || p < kPlanes / 2)
+            buf_store<S>(v, lo, voff, soff + unsigned(p) * PB);
+        else
+            buf_store<S>(v, hi, voff, soff + unsigned(p - kPlanes / 2) * PB);
+    }
+};
+
 // A value every lane of the wavefront holds, kept in a scalar register.
 __device__ __forceinline__ unsigned wave_uniform(unsigned v) {
     return unsigned(__builtin_amdgcn_readfirstlane(int(v)));
@@ -85,8 +115,8 @@ struct TbCols {
 // Loads the raw inputs of the intermediate step at (x, r) for the lane's column.  r is a row
 // of the grid; a row beyond a walled side is never consumed, and its caller passes any valid
 // row instead.  Every load is unconditional, so every field is defined on every path.
-template <typename S, bool PN>
-__device__ __forceinline__ void tb_load(__amdgpu_buffer_rsrc_t rs, __amdgpu_buffer_rsrc_t rm,
+template <typename S, bool PN, int NDESC>
+__device__ __forceinline__ void tb_load(const TbState<S, NDESC>& rs, __amdgpu_buffer_rsrc_t rm,
                                         const Geo& G, unsigned PB, unsigned RB,
                                         const TbCols& c, int r, TbRaw<S>& raw) {
     const bool onS = G.wallS && r == 0, onN = G.wallN && r == G.ny - 1;
@@ -107,20 +137,20 @@ __device__ __forceinline__ void tb_load(__amdgpu_buffer_rsrc_t rs, __amdgpu_buff
         raw.phi_f = raw.K_f = raw.phi = raw.K = S(1);
     }
     // f_i arrives from (xf - ex_i, yf - ey_i)
-    raw.f[0] = buf_load<S>(rs, c.f, s0);
-    raw.f[1] = buf_load<S>(rs, c.fw, s0 + PB);
-    raw.f[2] = buf_load<S>(rs, c.f, sm + 2 * PB);
-    raw.f[3] = buf_load<S>(rs, c.fe, s0 + 3 * PB);
-    raw.f[4] = buf_load<S>(rs, c.f, sp + 4 * PB);
-    raw.f[5] = buf_load<S>(rs, c.fw, sm + 5 * PB);
-    raw.f[6] = buf_load<S>(rs, c.fe, sm + 6 * PB);
-    raw.f[7] = buf_load<S>(rs, c.fe, sp + 7 * PB);
-    raw.f[8] = buf_load<S>(rs, c.fw, sp + 8 * PB);
-    raw.g[0] = buf_load<S>(rs, c.f, s0 + 9 * PB);
-    raw.g[1] = buf_load<S>(rs, c.fw, s0 + 10 * PB);
-    raw.g[2] = buf_load<S>(rs, c.f, sm + 11 * PB);
-    raw.g[3] = buf_load<S>(rs, c.fe, s0 + 12 * PB);
-    raw.g[4] = buf_load<S>(rs, c.f, sp + 13 * PB);
+    raw.f[0] = rs.load(0, c.f, s0);
+    raw.f[1] = rs.load(1, c.fw, s0);
+    raw.f[2] = rs.load(2, c.f, sm);
+    raw.f[3] = rs.load(3, c.fe, s0);
+    raw.f[4] = rs.load(4, c.f, sp);
+    raw.f[5] = rs.load(5, c.fw, sm);
+    raw.f[6] = rs.load(6, c.fe, sm);
+    raw.f[7] = rs.load(7, c.fe, sp);
+    raw.f[8] = rs.load(8, c.fw, sp);
+    raw.g[0] = rs.load(9, c.f, s0);
+    raw.g[1] = rs.load(10, c.fw, s0);
+    raw.g[2] = rs.load(11, c.f, sm);
+    raw.g[3] = rs.load(12, c.fe, s0);
+    raw.g[4] = rs.load(13, c.f, sp);
 }
 
 // The intermediate step at (x, r) from its raw inputs: node_state's arithmetic, then collide,
@@ -168,7 +198,7 @@ __device__ __forceinline__ int tb_row(const Geo& G, int r) {
 // wavefront of the work-group calls this with the same segment and runs the same rows (an
 // inactive one, past the last strip, stores nothing), since each row ends with a work-group
 // barrier.
-template <typename S, typename R, bool PN, bool REV>
+template <typename S, typename R, bool PN, bool REV, int NDESC>
 __device__ __forceinline__ void tb2_sweep(const S* __restrict__ src, S* __restrict__ dst,
                                           const S* __restrict__ med, const Geo& G,
                                           const Phys<R>& P, int strip, bool active, int seg,
@@ -177,8 +207,7 @@ __device__ __forceinline__ void tb2_sweep(const S* __restrict__ src, S* __restri
     constexpr int D = REV ? -1 : 1;              // direction of the sweep along y
     const unsigned PB = unsigned(G.plane) * B;   // bytes per plane
     const unsigned RB = unsigned(G.pitch) * B;   // bytes per row
-    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(src, 14 * PB);
-    const __amdgpu_buffer_rsrc_t rd = buf_rsrc(dst, 14 * PB);
+    const TbState<S, NDESC> rs(src, PB), rd(dst, PB);
     const __amdgpu_buffer_rsrc_t rm = buf_rsrc(med, PN ? 2 * PB : 0);
     const int lane = threadIdx.x & 63;
     const int x0 = strip * kTbCols;
@@ -212,18 +241,18 @@ __device__ __forceinline__ void tb2_sweep(const S* __restrict__ src, S* __restri
     {
         Med<R> unused;
         int r = tb_row(G, yb - D);
-        tb_load<S, PN>(rs, rm, G, PB, RB, cols, r, raw);
+        tb_load<S, PN, NDESC>(rs, rm, G, PB, RB, cols, r, raw);
         tb_finish<S, R, PN>(raw, G, P, x, r, bh, unused);
         r = tb_row(G, yb);
-        tb_load<S, PN>(rs, rm, G, PB, RB, cols, r, raw);
+        tb_load<S, PN, NDESC>(rs, rm, G, PB, RB, cols, r, raw);
         tb_finish<S, R, PN>(raw, G, P, x, r, cur, mdb);
-        tb_load<S, PN>(rs, rm, G, PB, RB, cols, tb_row(G, yb + D), raw);
+        tb_load<S, PN, NDESC>(rs, rm, G, PB, RB, cols, tb_row(G, yb + D), raw);
         // 14 stores that the hardware drops, so that on entering the row loop, as on every
         // later row, the loads in flight are followed by 14 stores: the compiler's wait for
         // those loads at the top of the loop then leaves the previous row's stores in flight
         __builtin_amdgcn_sched_barrier(0);  // keep them after the loads
 #pragma unroll
-        for (int i = 0; i < 14; ++i) buf_store<S>(S(0), rd, kBufOutOfRange, i * PB);
+        for (int i = 0; i < 14; ++i) rd.store(S(0), i, kBufOutOfRange, 0);
     }
     // the last row's loads would fetch a row that nothing uses: out of range, they return zero
     // without a memory access
@@ -233,7 +262,8 @@ __device__ __forceinline__ void tb2_sweep(const S* __restrict__ src, S* __restri
     do {
         tb_finish<S, R, PN>(raw, G, P, x, tb_row(G, y + D), ah, mdn);
         // issue the next row's loads now; they complete during this row's work
-        tb_load<S, PN>(rs, rm, G, PB, RB, y + D == ye ? none : cols, tb_row(G, y + 2 * D), raw);
+        tb_load<S, PN, NDESC>(rs, rm, G, PB, RB, y + D == ye ? none : cols, tb_row(G, y + 2 * D),
+                              raw);
         // step n+1 at rows y - 1 and y + 1, whichever way the sweep runs
         const S* dn = REV ? ah : bh;   // row y - 1
         const S* up = REV ? bh : ah;   // row y + 1
@@ -261,10 +291,9 @@ __device__ __forceinline__ void tb2_sweep(const S* __restrict__ src, S* __restri
                     const unsigned ob =
                         (unsigned(yb2) * unsigned(G.pitch) + unsigned(xb)) * B;
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) buf_store<S>(S(fb[i]), rd, ob, i * PB);
+                    for (int i = 0; i < 9; ++i) rd.store(S(fb[i]), i, ob, 0);
 #pragma unroll
-                    for (int i = 0; i < 5; ++i)
-                        buf_store<S>(S(gb[i]), rd, ob, (9 + i) * PB);
+                    for (int i = 0; i < 5; ++i) rd.store(S(gb[i]), 9 + i, ob, 0);
                 });
         collide<R>(f, g, m, md, P);
         // plain stores: a strip's edge lines are shared with its neighbour, and merge in L2
@@ -272,9 +301,9 @@ __device__ __forceinline__ void tb2_sweep(const S* __restrict__ src, S* __restri
         const unsigned vo = own ? cols.x : kBufOutOfRange;
         const unsigned sy = wave_uniform(unsigned(y) * RB);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) buf_store<S>(S(f[i]), rd, vo, sy + i * PB);
+        for (int i = 0; i < 9; ++i) rd.store(S(f[i]), i, vo, sy);
 #pragma unroll
-        for (int i = 0; i < 5; ++i) buf_store<S>(S(g[i]), rd, vo, sy + (9 + i) * PB);
+        for (int i = 0; i < 5; ++i) rd.store(S(g[i]), 9 + i, vo, sy);
 #pragma unroll
         for (int i = 0; i < 14; ++i) {
             bh[i] = cur[i];
@@ -292,15 +321,15 @@ __device__ __forceinline__ void tb2_sweep(const S* __restrict__ src, S* __restri
 // the same time, at both ends of the sweep: running side by side on one XCD, the second reads
 // them from L2 instead of memory.  (Swept the same way, the second reached those rows ~rows
 // iterations later, after some 2 MB per iteration per XCD had gone through its 4 MB L2.)
-template <typename S, typename R, bool PN>
+template <typename S, typename R, bool PN, int NDESC = 1>
 __device__ __forceinline__ void tb2_segment(const S* __restrict__ src, S* __restrict__ dst,
                                             const S* __restrict__ med, const Geo& G,
                                             const Phys<R>& P, int strip, bool active, int seg,
                                             int rows) {
     if (seg & 1)
-        tb2_sweep<S, R, PN, true>(src, dst, med, G, P, strip, active, seg, rows);
+        tb2_sweep<S, R, PN, true, NDESC>(src, dst, med, G, P, strip, active, seg, rows);
     else
-        tb2_sweep<S, R, PN, false>(src, dst, med, G, P, strip, active, seg, rows);
+        tb2_sweep<S, R, PN, false, NDESC>(src, dst, med, G, P, strip, active, seg, rows);
 }
 
 // Work-groups are dealt round-robin over the 8 XCDs.  This maps a launch's work-group index to a

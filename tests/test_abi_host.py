@@ -189,15 +189,21 @@ def test_a_batch_has_no_tile_form(lbm):
     assert _abi.library().lbm_batch_workspace_size(2, p, C.byref(n)) == -6   # UNSUPPORTED
 
 
-def test_two_steps_per_launch_need_a_state_below_2_gib(lbm):
-    """The two-step kernels address a state through one buffer descriptor and drop the stores of
-    lanes that own no node through an offset of 2^31, so the state must stay below 2^31 bytes."""
-    # 14 planes x 3500 rows x pitch 3520 x 8 B = 1.38 GB in FP64; 4400^2 is 2.17 GB
+def test_two_steps_per_launch_need_each_half_of_the_state_below_2_gib(lbm):
+    """The two-step kernel addresses a state through buffer descriptors (one for a state below
+    2^31 bytes, else two: planes 0-6 and 7-13) and drops the stores of lanes that own no node
+    through an offset of 2^31, so each descriptor must cover less than 2^31 bytes."""
+    # FP64: 4400^2 is 2.17 GB (two descriptors of 1.08 GB); 6100^2 has 7 planes of 2.10 GB in
+    # all, 6200^2 of 2.16 GB
     assert status_of(lbm, nx=3500, ny=3500, dtype=1, steps_per_launch=2) == 0
-    assert status_of(lbm, nx=4400, ny=4400, dtype=1, steps_per_launch=2) == -6  # UNSUPPORTED
-    assert status_of(lbm, nx=4400, ny=4400, dtype=1, steps_per_launch=0) == 0   # single steps
-    assert status_of(lbm, nx=4096, ny=4096, dtype=1, steps_per_launch=2) == 0   # 1.88 GB
-    assert status_of(lbm, nx=6500, ny=6500, steps_per_launch=2) == -6           # FP32 2.37 GB
+    assert status_of(lbm, nx=4400, ny=4400, dtype=1, steps_per_launch=2) == 0
+    assert status_of(lbm, nx=6100, ny=6100, dtype=1, steps_per_launch=2) == 0
+    assert status_of(lbm, nx=6200, ny=6200, dtype=1, steps_per_launch=2) == -6  # UNSUPPORTED
+    assert status_of(lbm, nx=6200, ny=6200, dtype=1, steps_per_launch=0) == 0   # single steps
+    # FP32: 8700^2 has 7 planes of 2.12 GB, 8800^2 of 2.18 GB
+    assert status_of(lbm, nx=8700, ny=8700, steps_per_launch=2) == 0
+    assert status_of(lbm, nx=8800, ny=8800, steps_per_launch=2) == -6
+    # the batched two-step kernel takes one descriptor per cavity: below 2 GiB each
     from paper_1308_2071_amd import _abi
     big = lbm.make_params(nx=6500, ny=6500, steps_per_launch=0)
     small = lbm.make_params(nx=64, ny=64, steps_per_launch=2)

@@ -12,7 +12,8 @@
   against the oracle at every node;
 - two steps per launch at full size: bitwise equal to single steps over 1000 steps of the
   roofline4096 field (FP32 and FP64 arithmetic), and for FP64 storage at 4096^2, a state near
-  the two-step kernel's 2 GiB limit;
+  the one-descriptor limit of 2 GiB; states beyond it, addressed through two descriptors (FP32
+  8192^2, 3.8 GB, and FP64 6100^2, 4.2 GB, near the limit of that form);
 - adjoint256 (256 x 256, 2000 steps, checkpoint every 100): the HIP adjoint's dJ/deps at 16
   probes against central FP64 finite differences of the oracle (FP32 within 1e-3 of max |grad|,
   FP64 arithmetic on FP32 storage 1e-4, FP64 within the differences' own 3e-5), and dJ/dphi,
@@ -172,6 +173,36 @@ def test_fp64_4096_fused_state_near_the_2_gib_limit_equals_single_steps():
     assert a["nu_hot"] == b["nu_hot"]
     fused.close()
     single.close()
+
+
+@pytest.mark.parametrize("case", ["fp32_8192", "fp64_6100"])
+def test_two_descriptor_states_fused_equals_single_steps(case):
+    """States of 2 GiB or more go through two buffer descriptors, planes 0-6 and 7-13, each below
+    2^31 bytes.  FP32 at 8192^2 (3.8 GB per state, the roofline medium tiled 2 x 2) and FP64 at
+    6100^2 (4.2 GB, each half 2.10 GB: the largest offsets this form allows, and the dropped
+    stores 2 GiB past them): fused equals single steps bitwise, with an odd step count."""
+    if case == "fp32_8192":
+        w = workloads.roofline4096()
+        phi = torch.from_numpy(np.tile(w["phi"].astype(np.float32), (2, 2)))
+        K = torch.from_numpy(np.tile(w["K"].astype(np.float32), (2, 2)))
+        params = dict(w["params"], nx=8192, ny=8192, dtype="fp32")
+        kw = dict(phi=phi, K=K)
+    else:
+        params = dict(workloads.cavity(6100, Ra=1e6, Pr=0.71, Da=1e-3), dtype="fp64")
+        kw = dict(phi_uniform=0.6)
+    fused = Cavity(dict(params, steps_per_launch=2), **kw)
+    single = Cavity(dict(params, steps_per_launch=1), **kw)
+    assert lbm_step_shape(fused.ctx)[0] == 2
+    fused.step(101)
+    single.step(101)
+    a, b = fused.observables(), single.observables()
+    for k in FIELDS:
+        assert torch.equal(a[k], b[k]), k
+    assert a["nu_hot"] == b["nu_hot"]
+    fused.close()
+    single.close()
+    del a, b, kw
+    torch.cuda.empty_cache()
 
 
 def test_largest_grid_the_state_limit_allows_fp64_against_oracle():
