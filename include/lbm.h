@@ -105,7 +105,7 @@ typedef struct {
                              /* faster (large grids, storage type = arithmetic type), four   */
                              /* (16 x 16 tiles advanced in LDS) where that is (small grids), */
                              /* else one.  1: one.  2: two; it needs each half of the state  */
-                             /* (7 of the 14 planes) below 2 GiB and gives                    */
+                             /* (7 of the 14 planes) below 2 GiB and gives                   */
                              /* LBM_E_UNSUPPORTED beyond.  4: four.                          */
                              /* With a tape, launches of two or four steps run only between  */
                              /* checkpoints.  The AA layout steps one at a time.             */
