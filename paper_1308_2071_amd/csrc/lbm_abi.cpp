@@ -158,9 +158,9 @@ lbm_status validate(const lbm_params& p) {
     if (p.layout != LBM_LAYOUT_PULL && p.layout != LBM_LAYOUT_AA)
         return fail(LBM_E_INVAL, "layout %d is not LBM_LAYOUT_PULL or LBM_LAYOUT_AA", p.layout);
     if (p.steps_per_launch != 0 && p.steps_per_launch != 1 && p.steps_per_launch != 2 &&
-        p.steps_per_launch != kTileSteps)
-        return fail(LBM_E_INVAL, "steps_per_launch = %d is not 0, 1, 2 or %d", p.steps_per_launch,
-                    kTileSteps);
+        p.steps_per_launch != kTileSteps && p.steps_per_launch != kTinyTileSteps)
+        return fail(LBM_E_INVAL, "steps_per_launch = %d is not 0, 1, 2, %d or %d",
+                    p.steps_per_launch, kTileSteps, kTinyTileSteps);
     if (p.steps_per_launch == 2 &&
         plane_elems(pitch, p.ny) * (kPlanes / 2) * (long long)storage_bytes(p.dtype) >= (1LL << 31))
         return fail(LBM_E_UNSUPPORTED,
@@ -395,7 +395,7 @@ hipError_t advance(lbm_ctx* c, int from, hipStream_t s) {
 }
 
 // k > 1 steps in one launch from buffer `from` (pull layout only): the two-step kernel for
-// k = 2, the tiles in LDS for k = kTileSteps.
+// k = 2, the tiles in LDS for k = kTileSteps or kTinyTileSteps.
 hipError_t advance_k(lbm_ctx* c, int k, int from, hipStream_t s) {
     return with_types(c->p.dtype, [&](auto st, auto rt) {
         LBM_TYPES(st, rt)
@@ -403,13 +403,13 @@ hipError_t advance_k(lbm_ctx* c, int k, int from, hipStream_t s) {
             return launch_tb2_step<S, R>(c->buf(from), c->buf(1 - from), c->medp(), c->G,
                                          phys<R>(c), s);
         return launch_tile_step<S, R>(c->buf(from), c->buf(1 - from), c->medp(), c->G,
-                                      phys<R>(c), s);
+                                      phys<R>(c), k, s);
     });
 }
 
 // Time steps per launch of the time loop: one with the AA layout; steps_per_launch when it
-// asks for 1, 2 or kTileSteps; by default two (the two-step kernel) where that is measured to
-// pay, else kTileSteps (the tiles in LDS) where that is, else one.  With a tape, launches of
+// asks for 1, 2, kTileSteps or kTinyTileSteps; by default two (the two-step kernel) where that
+// is measured to pay, else the tiles in LDS where a form of them does, else one.  With a tape, launches of
 // several steps run only between checkpoints (lbm_step).
 int launch_steps(const lbm_ctx* c) {
     if (c->p.layout != LBM_LAYOUT_PULL) return 1;
@@ -417,7 +417,8 @@ int launch_steps(const lbm_ctx* c) {
     return with_types(c->p.dtype, [&](auto st, auto rt) {
         LBM_TYPES(st, rt)
         if (tb2_pays<S, R>(c->G, c->med)) return 2;
-        return tile_pays<S, R>(c->G, c->med) ? kTileSteps : 1;
+        const int t = tile_steps<S, R>(c->G, c->med);
+        return t > 0 ? t : 1;
     });
 }
 
@@ -509,7 +510,8 @@ lbm_status batch_layout(int32_t n, const lbm_params* p, BatchLayout* L) {
             return fail(LBM_E_UNSUPPORTED, "cavity %d: no adjoint tape in a batch", i);
         if (p[i].layout != LBM_LAYOUT_PULL)
             return fail(LBM_E_UNSUPPORTED, "cavity %d: a batch uses the pull layout", i);
-        if (i == 0 && p[0].steps_per_launch == kTileSteps)
+        if (i == 0 && (p[0].steps_per_launch == kTileSteps ||
+                       p[0].steps_per_launch == kTinyTileSteps))
             return fail(LBM_E_UNSUPPORTED, "a batch steps one or two steps per launch");
         const Geo G = make_geo(p[i]);
         if (p[0].steps_per_launch == 2 && tb2_descs(G, storage_bytes(dt)) != 1)
@@ -1493,9 +1495,10 @@ lbm_status lbm_step_shape(const lbm_ctx* c, int32_t* out) {
     out[1] = c->p.layout;
     out[2] = 0;
     out[3] = (c->G.nx + kTileX - 1) / kTileX * c->G.ny;
-    if (k == kTileSteps) {
-        out[2] = kTileSide;
-        out[3] = (c->G.nx + kTileSide - 1) / kTileSide * ((c->G.ny + kTileSide - 1) / kTileSide);
+    if (k == kTileSteps || k == kTinyTileSteps) {
+        const int ts = tile_side(k);
+        out[2] = ts;
+        out[3] = (c->G.nx + ts - 1) / ts * ((c->G.ny + ts - 1) / ts);
     }
     if (k == 2)
         (void)with_types(c->p.dtype, [&](auto st, auto rt) {

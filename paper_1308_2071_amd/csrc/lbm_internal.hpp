@@ -38,11 +38,18 @@ constexpr int tb_min_waves() {
     return sizeof(S) == 4 && sizeof(R) == 4 ? 4 : 1;
 }
 
-// Several steps per launch on small grids (lbm_tile.hip): tile side, steps per launch and
-// threads per work-group.
+// Several steps per launch on small grids (lbm_tile.hip), in two forms of the same region
+// (a tile, a halo as wide as the steps, and one node more at a wall: 25 x 25 nodes at most):
+// 16 x 16 tiles advanced four steps, and on the smallest grids 8 x 8 tiles advanced eight.
 constexpr int kTileSide = 16;
 constexpr int kTileSteps = 4;
+constexpr int kTinyTileSide = 8;
+constexpr int kTinyTileSteps = 8;
 constexpr int kTileThreads = 640;   // one work-item per node of the largest region (25^2)
+static_assert(kTileSide + 2 * kTileSteps == kTinyTileSide + 2 * kTinyTileSteps,
+              "both tile forms share one region size");
+// Tile side of the form that takes k steps per launch
+constexpr int tile_side(int k) { return k == kTinyTileSteps ? kTinyTileSide : kTileSide; }
 
 // The two-step kernels address a state (the 14 planes) through raw buffer descriptors and drop
 // stores through an offset of 2^31 past them, so a descriptor covers less than 2^31 bytes: one
@@ -69,13 +76,15 @@ void prepare_tb2();
 // Whether two steps per launch are faster than one for this grid and these types
 template <typename S, typename R>
 bool tb2_pays(const Geo& G, bool per_node_medium);
-// Whether kTileSteps steps per launch in LDS are faster than one for this grid and these types
+// Steps per launch of the tile form that is fastest for this grid and these types, if one beats
+// a step per launch (kTileSteps or kTinyTileSteps), else 0
 template <typename S, typename R>
-bool tile_pays(const Geo& G, bool per_node_medium);
-// kTileSteps steps of the pull layout from src to dst, each tile of the grid advanced in LDS
+int tile_steps(const Geo& G, bool per_node_medium);
+// k (kTileSteps or kTinyTileSteps) steps of the pull layout from src to dst, each tile of the
+// grid advanced in LDS
 template <typename S, typename R>
 hipError_t launch_tile_step(const void* src, void* dst, const void* med, const Geo& G,
-                            const Phys<R>& P, hipStream_t s);
+                            const Phys<R>& P, int k, hipStream_t s);
 // Rows per segment and work-groups per launch of the two-step kernel
 template <typename S, typename R>
 void tb2_shape(const Geo& G, bool per_node_medium, int* rows, int* nwg);

@@ -1,5 +1,6 @@
 // lbm_tile.hip -- several time steps per launch on small grids: each work-group advances one
-// square tile of the lattice kTileSteps steps in LDS.
+// square tile of the lattice several steps in LDS (16 x 16 tiles four steps, or on the smallest
+// grids 8 x 8 tiles eight steps).
 #include "lbm_device.hpp"
 #include "lbm_internal.hpp"
 
@@ -7,12 +8,11 @@ namespace lbm {
 
 // On a small grid a step is a few microseconds of fixed cost (the launch, one round of loads
 // from L2, the drain of the stores) around a short computation, and one step per launch pays
-// that cost every step.  Here a work-group loads its tile of kTileSide x kTileSide nodes plus a
-// halo of kTileSteps nodes on each open side (and one more where the tile is one node thick at
-// a walled end, so that its wall nodes' inward neighbours are covered), runs kTileSteps steps
-// on the region in LDS (two buffers, in turn), and writes the tile back: bitwise the result of
-// kTileSteps launches of step_kernel (same per-node arithmetic, and the LDS holds the storage
-// type as a store would round it).
+// that cost every step.  Here a work-group loads its tile of TS x TS nodes plus a halo of K
+// nodes on each open side (and one more where the tile is one node thick at a walled end, so
+// that its wall nodes' inward neighbours are covered), runs K steps on the region in LDS (two
+// buffers, in turn), and writes the tile back: bitwise the result of K launches of step_kernel
+// (same per-node arithmetic, and the LDS holds the storage type as a store would round it).
 //
 // A region node can take step s when every value it reads is valid after step s - 1.  With d
 // the node's distance to the region's open sides (a side is closed where it is a wall of the
@@ -21,7 +21,7 @@ namespace lbm {
 // take every step.  Nodes that cannot are skipped; their stale values are read by no node that
 // takes the step.
 
-// LDS row stride and plane stride of a region (its largest side).
+// LDS row stride and plane stride of a region (its largest side; the same for both forms).
 constexpr int kTileRegion = kTileSide + 2 * kTileSteps + 1;
 constexpr int kTilePlane = kTileRegion * kTileRegion;
 
@@ -66,7 +66,7 @@ __device__ __forceinline__ int tile_wrap(int r, int n, bool periodic) {
     return r < 0 ? r + n : r;
 }
 
-template <typename S, typename R, bool PN>
+template <typename S, typename R, bool PN, int TS, int K>
 __global__ __launch_bounds__(kTileThreads) void tile_step_kernel(const S* __restrict__ src,
                                                                  S* __restrict__ dst,
                                                                  const S* __restrict__ med,
@@ -76,11 +76,12 @@ __global__ __launch_bounds__(kTileThreads) void tile_step_kernel(const S* __rest
     S* const buf0 = reinterpret_cast<S*>(tile_lds);
     S* const buf1 = buf0 + kPlanes * kTilePlane;
     S* const mlds = buf1 + kPlanes * kTilePlane;   // phi, K (per-node medium only)
-    constexpr int K = kTileSteps, W = kTileRegion;
+    constexpr int W = kTileRegion;
+    static_assert(TS + 2 * K + 1 <= kTileRegion, "region larger than the LDS planes");
 
     const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
-    const int x0 = tx * kTileSide, y0 = ty * kTileSide;
-    const int x1 = min(x0 + kTileSide, G.nx), y1 = min(y0 + kTileSide, G.ny);
+    const int x0 = tx * TS, y0 = ty * TS;
+    const int x1 = min(x0 + TS, G.nx), y1 = min(y0 + TS, G.ny);
     // a tile one node thick at the east (north) wall has its wall nodes' inward neighbours one
     // node west (south) of it: one more halo node on that side
     const int hW = K + ((x1 - x0 == 1 && G.wallE) ? 1 : 0);
@@ -168,9 +169,9 @@ constexpr size_t tile_lds_bytes() {
     return (2 * kPlanes + (PN ? 2 : 0)) * size_t(kTilePlane) * sizeof(S);
 }
 
-// Whether kTileSteps steps per launch in LDS beat one step per launch (and the two-step
-// kernel, which the default tries first).  Measured on porous cavities (per-node medium /
-// uniform medium), MLUPS of the tiles over the best other form:
+// The tile form that beats one step per launch (and the two-step kernel, which the default
+// tries first), if any.  Measured on porous cavities (per-node medium / uniform medium), MLUPS
+// of 16 x 16 tiles advanced four steps over the best other form:
 //   FP32                        64^2 1.09 / 1.19, 128^2 1.36 / 1.49, 256^2 1.47 / 1.54,
 //                               512^2 1.12 / 1.00, 1024^2 0.97 / 0.90
 //   FP64                        64^2 0.91 / 1.14, 128^2 1.18 / 1.44, 256^2 1.31 / 1.50,
@@ -178,38 +179,66 @@ constexpr size_t tile_lds_bytes() {
 //   FP32 storage, FP64 arith.   64^2 0.93 / 1.17, 128^2 1.12 / 1.35, 256^2 1.28 / 1.41,
 //                               512^2 0.64 / 0.73
 // On larger grids the halo's redundant work (2.25x the tile's nodes for the first step) costs
-// more than the launches it saves.
-template <typename S, typename R>
-bool tile_pays(const Geo& G, bool per_node_medium) {
-    const long long n = (long long)G.nx * G.ny;
-    if (sizeof(R) == 4) return n <= 512LL * 512;
-    if (!per_node_medium) return n <= (sizeof(S) == 8 ? 512LL * 512 : 256LL * 256);
-    return n >= 128LL * 128 && n <= 256LL * 256;
-}
+// more than the launches it saves.  On the smallest grids 8 x 8 tiles advanced eight steps pay
+// the launch cost half as often and keep four times as many work-groups busy, at up to 9x
+// redundant work in the first step.  MLUPS of the 8 x 8 form over the 16 x 16 one (uniform /
+// per-node medium):
+//   FP32                        48^2 1.12 / 1.08, 64^2 1.36 / 1.34, 96^2 1.35 / 1.31,
+//                               128^2 1.17 / 1.17, 160^2 0.95 / 0.92
+//   FP64                        48^2 1.09 / 1.05, 64^2 1.22 / 1.25, 96^2 1.21 / 1.24,
+//                               128^2 1.15 / 1.15, 160^2 0.79 / 0.75
+//   FP32 storage, FP64 arith.   48^2 1.04 / 1.00, 64^2 1.19 / 1.20, 96^2 1.19 / 1.20,
+//                               128^2 1.10 / 1.11, 160^2 0.72 / 0.71
+// With FP64 arithmetic and a per-node medium below 64^2 neither form beats one step per launch.
+constexpr long long kTinyTileMaxNodes = 128LL * 128;
 
 template <typename S, typename R>
-hipError_t launch_tile_step(const void* src, void* dst, const void* med, const Geo& G,
-                            const Phys<R>& P, hipStream_t s) {
-    const int tiles_x = (G.nx + kTileSide - 1) / kTileSide;
-    const int nwg = tiles_x * ((G.ny + kTileSide - 1) / kTileSide);
+int tile_steps(const Geo& G, bool per_node_medium) {
+    const long long n = (long long)G.nx * G.ny;
+    if (n <= kTinyTileMaxNodes)
+        return sizeof(R) == 4 || !per_node_medium || n >= 64LL * 64 ? kTinyTileSteps : 0;
+    bool pays;
+    if (sizeof(R) == 4)
+        pays = n <= 512LL * 512;
+    else if (!per_node_medium)
+        pays = n <= (sizeof(S) == 8 ? 512LL * 512 : 256LL * 256);
+    else
+        pays = n >= 128LL * 128 && n <= 256LL * 256;
+    return pays ? kTileSteps : 0;
+}
+
+template <typename S, typename R, int TS, int K>
+hipError_t launch_tiles(const void* src, void* dst, const void* med, const Geo& G,
+                        const Phys<R>& P, hipStream_t s) {
+    const int tiles_x = (G.nx + TS - 1) / TS;
+    const int nwg = tiles_x * ((G.ny + TS - 1) / TS);
     if (med) {
         constexpr size_t lds = tile_lds_bytes<S, true>();
         static_assert(lds <= 160 * 1024, "tile region exceeds the LDS of a CU");
         static_assert(kTilePlane <= kTileThreads, "one work-item per region node");
-        tile_step_kernel<S, R, true><<<nwg, kTileThreads, lds, s>>>(
+        tile_step_kernel<S, R, true, TS, K><<<nwg, kTileThreads, lds, s>>>(
             (const S*)src, (S*)dst, (const S*)med, G, P, tiles_x);
     } else {
         constexpr size_t lds = tile_lds_bytes<S, false>();
-        tile_step_kernel<S, R, false><<<nwg, kTileThreads, lds, s>>>(
+        tile_step_kernel<S, R, false, TS, K><<<nwg, kTileThreads, lds, s>>>(
             (const S*)src, (S*)dst, nullptr, G, P, tiles_x);
     }
     return hipGetLastError();
 }
 
+template <typename S, typename R>
+hipError_t launch_tile_step(const void* src, void* dst, const void* med, const Geo& G,
+                            const Phys<R>& P, int k, hipStream_t s) {
+    if (k == kTinyTileSteps)
+        return launch_tiles<S, R, kTinyTileSide, kTinyTileSteps>(src, dst, med, G, P, s);
+    if (k == kTileSteps) return launch_tiles<S, R, kTileSide, kTileSteps>(src, dst, med, G, P, s);
+    return hipErrorInvalidValue;
+}
+
 #define LBM_TILE_INST(S, R)                                                                    \
-    template bool tile_pays<S, R>(const Geo&, bool);                                           \
+    template int tile_steps<S, R>(const Geo&, bool);                                           \
     template hipError_t launch_tile_step<S, R>(const void*, void*, const void*, const Geo&,    \
-                                               const Phys<R>&, hipStream_t);
+                                               const Phys<R>&, int, hipStream_t);
 LBM_TILE_INST(float, float)
 LBM_TILE_INST(double, double)
 LBM_TILE_INST(float, double)

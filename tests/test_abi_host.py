@@ -172,8 +172,10 @@ def test_aa_layout_halves_the_state_memory(lbm):
 def test_aa_layout_limits(lbm):
     assert status_of(lbm, layout=3) == -1                          # LBM_E_INVAL
     assert status_of(lbm, steps_per_launch=3) == -1
-    assert status_of(lbm, steps_per_launch=4) == 0                 # tiles in LDS
+    assert status_of(lbm, steps_per_launch=4) == 0                 # 16 x 16 tiles in LDS
+    assert status_of(lbm, steps_per_launch=8) == 0                 # 8 x 8 tiles in LDS
     assert status_of(lbm, steps_per_launch=5) == -1
+    assert status_of(lbm, steps_per_launch=3) == -1
     assert status_of(lbm, layout=1, checkpoint_every=10) == -6     # LBM_E_UNSUPPORTED: no tape
     from paper_1308_2071_amd import _abi
     p = (_abi.LbmParams * 1)(lbm.make_params(nx=16, ny=16, layout="aa"))
@@ -181,9 +183,10 @@ def test_aa_layout_limits(lbm):
     assert _abi.library().lbm_batch_workspace_size(1, p, C.byref(n)) == -6
 
 
-def test_a_batch_has_no_tile_form(lbm):
+@pytest.mark.parametrize("spl", [4, 8])
+def test_a_batch_has_no_tile_form(lbm, spl):
     from paper_1308_2071_amd import _abi
-    p = (_abi.LbmParams * 2)(lbm.make_params(nx=32, ny=32, steps_per_launch=4),
+    p = (_abi.LbmParams * 2)(lbm.make_params(nx=32, ny=32, steps_per_launch=spl),
                              lbm.make_params(nx=32, ny=32))
     n = C.c_size_t()
     assert _abi.library().lbm_batch_workspace_size(2, p, C.byref(n)) == -6   # UNSUPPORTED
