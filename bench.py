@@ -304,12 +304,13 @@ def timed_call(fn, torch):
 def leg_porous64(torch):
     """The 64^2 FP64 cavity (phi = 0.6, Da = 1e-2, Ra = 1e3, Pr = 1), all 20k steps timed
     (launch-bound: 4096 nodes per step), and its Nu_hot (Table 2 gives 1.012 on 120^2)."""
-    from paper_1308_2071_amd import Cavity, workloads
+    from paper_1308_2071_amd import Cavity, lbm_step_shape, workloads
     w = workloads.porous64()
     c = Cavity(dict(w["params"], dtype="fp64"), phi_uniform=w["phi"])
     c.step(128)
     c.close()
     c = Cavity(dict(w["params"], dtype="fp64"), phi_uniform=w["phi"])
+    shape = [int(v) for v in lbm_step_shape(c.ctx)]
     secs = timed_steps(c, w["steps"], torch)
     o = c.observables(fields=False)
     c.close()
@@ -318,6 +319,7 @@ def leg_porous64(torch):
             "steps": w["steps"], "value": round(mlups, 1), "unit": "MLUPS",
             "us_per_step": round(secs / w["steps"] * 1e6, 3),
             "effective_GBps": round(mlups * 1e6 * BYTES_PER_NODE_FP64_UNIFORM / 1e9, 1),
+            "steps_per_launch": shape[0], "tile_side": shape[2],
             "nu_hot": o["nu_hot"], "diverged": o["diverged"]}
 
 
@@ -329,7 +331,7 @@ def leg_porous256(torch, steps=2000):
     field over the oracle field's range (p less its rest value, raw, and for FP32 storage also
     up to a uniform shift of phi p, the step's free pressure level), and |Nu_hot - oracle|."""
     import numpy as np
-    from paper_1308_2071_amd import Cavity, workloads
+    from paper_1308_2071_amd import Cavity, lbm_step_shape, workloads
     w = workloads.porous256()
     gold = np.load(os.path.join(ROOT, "tests", "golden", "porous256.npz"))
     out = {"workload": "256x256, phi 0.4, Da 1e-2, Ra 1e5, Pr 1", "steps": steps,
@@ -338,6 +340,7 @@ def leg_porous256(torch, steps=2000):
                     ("fp32_f64", BYTES_PER_NODE_FP32_UNIFORM),
                     ("fp64", BYTES_PER_NODE_FP64_UNIFORM)):
         c = Cavity(dict(w["params"], dtype=dt), phi_uniform=w["phi"])
+        shape = [int(v) for v in lbm_step_shape(c.ctx)]
         c.step(128)
         secs = timed_steps(c, steps, torch)
         c.close()
@@ -358,6 +361,7 @@ def leg_porous256(torch, steps=2000):
                 err["p_phip_gauge"] = float(f"{np.abs(d - c).max() / rng:.3e}")
         out[dt] = {"mlups": round(mlups, 1),
                    "effective_GBps": round(mlups * 1e6 * bpn / 1e9, 1),
+                   "steps_per_launch": shape[0], "tile_side": shape[2],
                    "nu_hot": o["nu_hot"], "nu_err": float(f"{abs(o['nu_hot'] - float(gold['nu_hot'])):.3e}"),
                    "field_err_of_range": err}
     out["oracle_nu_hot"] = float(gold["nu_hot"])
