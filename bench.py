@@ -8,8 +8,8 @@ FP32 storage, inputs resident in HBM before timing.  A step is one full time ste
 arithmetic (--dtype fp32, the default) or FP64 arithmetic on the same FP32 storage
 (--dtype fp32_f64).  The library's default time loop is timed: on this grid in FP32 it fuses two
 steps per launch.  Extra legs: one step per launch, the other arithmetic type, the AA layout,
-the batched form, the adjoint and the 256^2 cavity in every precision with its error against
-the oracle.
+the batched form, the adjoint, the 64^2 FP64 cavity, and the 256^2 cavity in every precision
+with its error against the oracle (the small grids report the launch form they ran).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--dtype D] [--no-cpu] [--no-extras]
 
