@@ -6,8 +6,9 @@ phi ~ U[0.3, 0.9] (seeded), Kozeny-Carman permeability with mean Da = 1e-3, Ra =
 FP32 storage, inputs resident in HBM before timing.  A step is one full time step of every node
 (pull streaming, wall reconstruction, macroscopics, flow and thermal MRT collision), in FP32
 arithmetic (--dtype fp32, the default) or FP64 arithmetic on the same FP32 storage
-(--dtype fp32_f64).  The library's default time loop is timed: on this grid in FP32 it fuses two
-steps per launch.  Extra legs: one step per launch, the other arithmetic type, the AA layout,
+(--dtype fp32_f64).  The library's default time loop is timed: on this grid it fuses three steps
+per launch in FP32, two with FP64 arithmetic.  Extra legs: one and two steps per launch, the
+other arithmetic type, the AA layout,
 the batched form, the adjoint, the 64^2 FP64 cavity, and the 256^2 cavity in every precision
 with its error against the oracle (the small grids report the launch form they ran).
 
@@ -35,13 +36,15 @@ BYTES_PER_NODE_FP32_UNIFORM = 28 * 4
 BYTES_PER_NODE_FP64_UNIFORM = 28 * 8
 # counter profiles of the roofline workload's kernels, by kernel
 TRAFFIC_PROFILES = {
+    "tb3_step_kernel<float,float,true>": os.path.join(ROOT, "profiles",
+                                                      "tb3_step_kernel_fp32_4096_traffic.md"),
     "tb2_step_kernel<float,float,true>": os.path.join(ROOT, "profiles",
                                                       "tb2_step_kernel_fp32_4096_traffic.md"),
     "step_kernel<float,float,true>": os.path.join(ROOT, "profiles",
                                                   "step_kernel_fp32_4096_traffic.md"),
 }
 STEP_SOURCES = ("paper_1308_2071_amd/csrc/lbm_device.hpp", "paper_1308_2071_amd/csrc/lbm_tb2.hpp",
-                "paper_1308_2071_amd/csrc/lbm_kernels.hip",
+                "paper_1308_2071_amd/csrc/lbm_tb3.hpp", "paper_1308_2071_amd/csrc/lbm_kernels.hip",
                 "paper_1308_2071_amd/csrc/lbm_internal.hpp",
                 "paper_1308_2071_amd/build.py")
 
@@ -77,7 +80,7 @@ def parse():
     ap.add_argument("--n", type=int, default=4096, help="grid side of the roofline workload")
     ap.add_argument("--dtype", default="fp32", choices=("fp32", "fp32_f64"),
                     help="roofline leg: FP32 storage with FP32 or FP64 arithmetic")
-    ap.add_argument("--steps-per-launch", type=int, default=0, choices=(0, 1, 2),
+    ap.add_argument("--steps-per-launch", type=int, default=0, choices=(0, 1, 2, 3),
                     help="roofline leg: 0 the library's choice, 1 or 2 forced")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip batched / adjoint / FP64 legs")
@@ -372,9 +375,10 @@ ARITH = {"fp32": "float", "fp32_f64": "double"}
 
 
 def kernel_name(dtype, shape):
-    """The kernel the roofline workload ran: the two-step kernel when the time loop fused two
-    steps per launch (lbm_step_shape), else the single-step one; FP32 storage."""
-    base = "tb2_step_kernel" if shape[0] == 2 else "step_kernel"
+    """The kernel the roofline workload ran: the three- or two-step kernel when the time loop
+    fused three or two steps per launch (lbm_step_shape), else the single-step one; FP32
+    storage."""
+    base = {3: "tb3_step_kernel", 2: "tb2_step_kernel"}.get(shape[0], "step_kernel")
     return f"{base}<float,{ARITH[dtype]},true>"
 
 
@@ -400,12 +404,12 @@ def roofline_run(torch, w, dtype, steps, warmup, layout="pull", steps_per_launch
 
 
 def roofline_obj(run):
-    """Roofline of the run's kernel.  achieved = the method's algorithmic 120 B per node update
-    x the node updates one launch makes (two when two steps are fused) / the launch's average
-    duration.  traffic = the HBM bytes one launch moves, from the committed counter profile of
-    that kernel (null when the kernel changed since); for the fused kernel they are about 0.6
-    of the algorithmic bytes of its two updates, which is what lets `achieved` pass the copy
-    ceiling of a single step."""
+    """Roofline of the run's kernel.  achieved = the method's algorithmic 120 B per node
+    update x the node updates one launch makes (two or three when steps are fused) / the
+    launch's average duration.  traffic = the HBM bytes one launch moves, from the committed counter profile of
+    that kernel (null when the kernel changed since); for the fused kernels they are well below
+    the algorithmic bytes of their updates, which is what lets `achieved` pass the copy ceiling
+    of a single step."""
     spl = run["shape"][0]
     launch_ms = run["ms"] * spl
     traffic = measured_traffic(run["kernel"])
@@ -418,7 +422,7 @@ def roofline_obj(run):
     own_min = BYTES_PER_NODE_FP32 * run["nodes"]
     out["own_min_bytes_per_launch"] = own_min
     out["frac_own_min"] = round(own_min / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-    if spl == 2:
+    if spl in (2, 3):
         out["rows_per_segment"] = run["shape"][2]
     if traffic is not None:
         out["measured_hbm_GBps"] = round(traffic / (launch_ms * 1e-3) / 1e9, 1)
@@ -504,6 +508,10 @@ def main():
         print("# roofline workload, one step per launch", file=sys.stderr, flush=True)
         o = roofline_run(torch, w, args.dtype, short, args.warmup, steps_per_launch=1)
         result["roofline_single_step"] = extra_leg(o, short, mlups, roofline=roofline_obj(o))
+        if run["shape"][0] != 2:
+            print("# roofline workload, two steps per launch", file=sys.stderr, flush=True)
+            o = roofline_run(torch, w, args.dtype, short, args.warmup, steps_per_launch=2)
+            result["roofline_two_steps"] = extra_leg(o, short, mlups, roofline=roofline_obj(o))
         other = "fp32_f64" if args.dtype == "fp32" else "fp32"
         print(f"# roofline workload in {other}", file=sys.stderr, flush=True)
         o = roofline_run(torch, w, other, short, args.warmup)

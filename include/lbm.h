@@ -100,16 +100,19 @@ typedef struct {
     int32_t dtype;           /* LBM_FP32, LBM_FP64 or LBM_FP32_F64                            */
     int32_t checkpoint_every;/* 0: no adjoint tape; C > 0: checkpoint every C steps, lbm_grad on */
     int32_t layout;          /* LBM_LAYOUT_PULL (default) or LBM_LAYOUT_AA                     */
-    int32_t steps_per_launch;/* Time steps per launch of the pull layout.  0 (default): two  */
-                             /* (the intermediate step kept in registers) where that is      */
+    int32_t steps_per_launch;/* Time steps per launch of the pull layout.  0 (default):     */
+                             /* three (FP32 on grids of about 2048^2 and more) or two (the   */
+                             /* intermediate steps kept in registers and LDS) where that is  */
                              /* faster (large grids, storage type = arithmetic type), four   */
                              /* (16 x 16 tiles advanced in LDS) or eight (8 x 8 tiles) where */
                              /* that is (small and the smallest grids), else one.  1: one.   */
                              /* 2: two; it needs each half of the state (7 of the 14 planes) */
-                             /* below 2 GiB and gives LBM_E_UNSUPPORTED beyond.  4: four.    */
-                             /* 8: eight.  With a tape, launches of several steps run only   */
-                             /* between checkpoints.  The AA layout steps one at a time.     */
-                             /* Results are bitwise the same in every case.                  */
+                             /* below 2 GiB and gives LBM_E_UNSUPPORTED beyond.  3: three;   */
+                             /* it needs LBM_FP32 and the whole state below 2 GiB, else      */
+                             /* LBM_E_UNSUPPORTED.  4: four.  8: eight.  With a tape,        */
+                             /* launches of several steps run only between checkpoints.  The */
+                             /* AA layout steps one at a time.  Results are bitwise the same */
+                             /* in every case.                                               */
 } lbm_params;
 
 /* Reasons for the divergence flag (bits of lbm_obs.why).  The paper gives no divergence test;
@@ -199,9 +202,9 @@ lbm_status lbm_observables(lbm_ctx* c, lbm_obs* o, void* ux, void* uy, void* p, 
 lbm_status lbm_stream_function(lbm_ctx* c, void* psi);
 
 /* Launch shape of the time loop in use (no device work): out[0] time steps per launch (1, 2,
- * 4 or 8, see steps_per_launch), out[1] the layout (LBM_LAYOUT_*), out[2] rows per wavefront
- * segment of the two-step kernel, or the tile side (16 or 8) of the tile forms (0 for one step
- * per launch), out[3] work-groups per launch.  out holds 4 entries. */
+ * 3, 4 or 8, see steps_per_launch), out[1] the layout (LBM_LAYOUT_*), out[2] rows per
+ * wavefront segment of the two- and three-step kernels, or the tile side (16 or 8) of the tile
+ * forms (0 for one step per launch), out[3] work-groups per launch.  out holds 4 entries. */
 lbm_status lbm_step_shape(const lbm_ctx* c, int32_t* out);
 
 /* Discrete adjoint (synchronises).  For J = nu_hot at the current time level n (Eq. (38)),
@@ -250,7 +253,7 @@ lbm_status lbm_batch_workspace_size(int32_t n, const lbm_params* p, size_t* byte
  * The autotuner also times two steps per launch and keeps it where it is faster;
  * p[0].steps_per_launch = 1 or 2 forces one or two (the other cavities' values are ignored;
  * 2 gives LBM_E_UNSUPPORTED if a cavity's state reaches 2 GiB, where the autotuner keeps one
- * step per launch; 4 and 8, the tiles of a single cavity, give LBM_E_UNSUPPORTED).  Results are
+ * step per launch; 3, 4 and 8, forms of a single cavity, give LBM_E_UNSUPPORTED).  Results are
  * bitwise the same either way. */
 lbm_status lbm_batch_init(lbm_ctx** out, int32_t n, const lbm_params* p,
                           const double* phi_uniform, void* workspace, size_t ws_bytes,

@@ -158,9 +158,14 @@ lbm_status validate(const lbm_params& p) {
     if (p.layout != LBM_LAYOUT_PULL && p.layout != LBM_LAYOUT_AA)
         return fail(LBM_E_INVAL, "layout %d is not LBM_LAYOUT_PULL or LBM_LAYOUT_AA", p.layout);
     if (p.steps_per_launch != 0 && p.steps_per_launch != 1 && p.steps_per_launch != 2 &&
-        p.steps_per_launch != kTileSteps && p.steps_per_launch != kTinyTileSteps)
-        return fail(LBM_E_INVAL, "steps_per_launch = %d is not 0, 1, 2, %d or %d",
+        p.steps_per_launch != 3 && p.steps_per_launch != kTileSteps &&
+        p.steps_per_launch != kTinyTileSteps)
+        return fail(LBM_E_INVAL, "steps_per_launch = %d is not 0, 1, 2, 3, %d or %d",
                     p.steps_per_launch, kTileSteps, kTinyTileSteps);
+    if (p.steps_per_launch == 3 &&
+        (p.dtype != LBM_FP32 ||
+         plane_elems(pitch, p.ny) * kPlanes * (long long)storage_bytes(p.dtype) >= (1LL << 31)))
+        return fail(LBM_E_UNSUPPORTED, "three steps per launch need FP32 and a state below 2 GiB");
     if (p.steps_per_launch == 2 &&
         plane_elems(pitch, p.ny) * (kPlanes / 2) * (long long)storage_bytes(p.dtype) >= (1LL << 31))
         return fail(LBM_E_UNSUPPORTED,
@@ -394,13 +399,16 @@ hipError_t advance(lbm_ctx* c, int from, hipStream_t s) {
     });
 }
 
-// k > 1 steps in one launch from buffer `from` (pull layout only): the two-step kernel for
-// k = 2, the tiles in LDS for k = kTileSteps or kTinyTileSteps.
+// k > 1 steps in one launch from buffer `from` (pull layout only): the two- and three-step
+// kernels for k = 2 and 3, the tiles in LDS for k = kTileSteps or kTinyTileSteps.
 hipError_t advance_k(lbm_ctx* c, int k, int from, hipStream_t s) {
     return with_types(c->p.dtype, [&](auto st, auto rt) {
         LBM_TYPES(st, rt)
         if (k == 2)
             return launch_tb2_step<S, R>(c->buf(from), c->buf(1 - from), c->medp(), c->G,
+                                         phys<R>(c), s);
+        if (k == 3)
+            return launch_tb3_step<S, R>(c->buf(from), c->buf(1 - from), c->medp(), c->G,
                                          phys<R>(c), s);
         return launch_tile_step<S, R>(c->buf(from), c->buf(1 - from), c->medp(), c->G,
                                       phys<R>(c), k, s);
@@ -408,14 +416,15 @@ hipError_t advance_k(lbm_ctx* c, int k, int from, hipStream_t s) {
 }
 
 // Time steps per launch of the time loop: one with the AA layout; steps_per_launch when it
-// asks for 1, 2, kTileSteps or kTinyTileSteps; by default two (the two-step kernel) where that
-// is measured to pay, else the tiles in LDS where a form of them does, else one.  With a tape, launches of
-// several steps run only between checkpoints (lbm_step).
+// asks for 1, 2, 3, kTileSteps or kTinyTileSteps; by default three (FP32) or two where that is
+// measured to pay, else the tiles in LDS where a form of them does, else one.  With a tape,
+// launches of several steps run only between checkpoints (lbm_step).
 int launch_steps(const lbm_ctx* c) {
     if (c->p.layout != LBM_LAYOUT_PULL) return 1;
     if (c->p.steps_per_launch != 0) return c->p.steps_per_launch;
     return with_types(c->p.dtype, [&](auto st, auto rt) {
         LBM_TYPES(st, rt)
+        if (tb3_pays<S, R>(c->G, c->med)) return 3;
         if (tb2_pays<S, R>(c->G, c->med)) return 2;
         const int t = tile_steps<S, R>(c->G, c->med);
         return t > 0 ? t : 1;
@@ -428,9 +437,13 @@ int pop_layout(const lbm_ctx* c) {
     return c->cur == 0 ? kAAOpp : kAAOwn;
 }
 
-// Capture kGraphSteps launches (an even count, so the buffers, or the AA parity, end where they
-// started) into an executable graph for the given starting buffer or parity.
-constexpr int kGraphSteps = 64;
+// Capture kGraphSteps steps into an executable graph for the given starting buffer or parity:
+// an even number of launches at every steps-per-launch count, so that the buffers, or the AA
+// parity, end where they started.
+constexpr int kGraphSteps = 48;
+static_assert(kGraphSteps % 2 == 0 && kGraphSteps % 4 == 0 && kGraphSteps % 6 == 0 &&
+                  kGraphSteps % (2 * kTileSteps) == 0 && kGraphSteps % (2 * kTinyTileSteps) == 0,
+              "kGraphSteps must be an even number of launches of each form");
 
 lbm_status ensure_graph(lbm_ctx* c, int start) {
     if (c->gexec[start]) return LBM_OK;
@@ -510,7 +523,7 @@ lbm_status batch_layout(int32_t n, const lbm_params* p, BatchLayout* L) {
             return fail(LBM_E_UNSUPPORTED, "cavity %d: no adjoint tape in a batch", i);
         if (p[i].layout != LBM_LAYOUT_PULL)
             return fail(LBM_E_UNSUPPORTED, "cavity %d: a batch uses the pull layout", i);
-        if (i == 0 && (p[0].steps_per_launch == kTileSteps ||
+        if (i == 0 && (p[0].steps_per_launch == 3 || p[0].steps_per_launch == kTileSteps ||
                        p[0].steps_per_launch == kTinyTileSteps))
             return fail(LBM_E_UNSUPPORTED, "a batch steps one or two steps per launch");
         const Geo G = make_geo(p[i]);
@@ -1500,11 +1513,14 @@ lbm_status lbm_step_shape(const lbm_ctx* c, int32_t* out) {
         out[2] = ts;
         out[3] = (c->G.nx + ts - 1) / ts * ((c->G.ny + ts - 1) / ts);
     }
-    if (k == 2)
+    if (k == 2 || k == 3)
         (void)with_types(c->p.dtype, [&](auto st, auto rt) {
             LBM_TYPES(st, rt)
-            int rows = 0, nwg = 0;
-            tb2_shape<S, R>(c->G, c->med, &rows, &nwg);
+            int rows = 0, nseg = 0, nwg = 0;
+            if (k == 2)
+                tb2_shape<S, R>(c->G, c->med, &rows, &nwg);
+            else
+                tb3_shape<S, R>(c->G, c->med, &rows, &nseg, &nwg);
             out[2] = rows;
             out[3] = nwg;
             return 0;

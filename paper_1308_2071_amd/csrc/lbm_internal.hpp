@@ -85,6 +85,16 @@ int tile_steps(const Geo& G, bool per_node_medium);
 template <typename S, typename R>
 hipError_t launch_tile_step(const void* src, void* dst, const void* med, const Geo& G,
                             const Phys<R>& P, int k, hipStream_t s);
+// Three steps per launch (FP32 storage and arithmetic only; hipErrorInvalidValue otherwise, or
+// for a state of 2 GiB or more): whether they are faster than two for this grid; rows per
+// segment, segments and work-groups per launch; the launch, src (step n) to dst (step n + 3)
+template <typename S, typename R>
+bool tb3_pays(const Geo& G, bool per_node_medium);
+template <typename S, typename R>
+void tb3_shape(const Geo& G, bool per_node_medium, int* rows, int* nseg, int* nwg);
+template <typename S, typename R>
+hipError_t launch_tb3_step(const void* src, void* dst, const void* med, const Geo& G,
+                           const Phys<R>& P, hipStream_t s);
 // Rows per segment and work-groups per launch of the two-step kernel
 template <typename S, typename R>
 void tb2_shape(const Geo& G, bool per_node_medium, int* rows, int* nwg);

@@ -4,6 +4,7 @@
 #include "lbm_device.hpp"
 #include "lbm_internal.hpp"
 #include "lbm_tb2.hpp"
+#include "lbm_tb3.hpp"
 
 namespace lbm {
 
@@ -78,6 +79,31 @@ __global__ __launch_bounds__(64 * kTbWaves, (tb_min_waves<S, R>())) void tb2_ste
     const int ngrp = (nstrips + kTbWaves - 1) / kTbWaves;
     const int strip = (wg % ngrp) * kTbWaves + (threadIdx.x >> 6), seg = wg / ngrp;
     tb2_segment<S, R, PN, NDESC>(src, dst, med, G, P, strip, strip < nstrips, seg, rows);
+}
+
+// Three steps per launch (FP32): a work-group holds kTb3Waves adjacent strips of one row
+// segment, each with its own ring of step n+2 rows in LDS, kept in step by a barrier per row.
+// Segments alternate their sweep direction, except that the segment at a south wall sweeps
+// forwards and the one at a north wall backwards; the last segment takes the rows left over.
+template <typename S, typename R, bool PN>
+__global__ __launch_bounds__(64 * kTb3Waves, 3) void tb3_step_kernel(const S* __restrict__ src,
+                                                                   S* __restrict__ dst,
+                                                                   const S* __restrict__ med,
+                                                                   Geo G, Phys<R> P, int nstrips,
+                                                                   int rows, int nseg,
+                                                                   int chunk) {
+    __shared__ S ring[kTb3Waves * kTb3Ring];
+    const int wg = tb_logical_group(chunk);
+    const int ngrp = (nstrips + kTb3Waves - 1) / kTb3Waves;
+    const int w = int(threadIdx.x) >> 6;
+    const int strip = (wg % ngrp) * kTb3Waves + w, seg = wg / ngrp;
+    const int ylo = seg * rows, yhi = seg == nseg - 1 ? G.ny : ylo + rows;
+    const bool rev = (G.wallN && seg == nseg - 1) || (!(G.wallS && seg == 0) && (seg & 1));
+    S* const my = ring + w * kTb3Ring;
+    if (rev)
+        tb3_sweep<S, R, PN, true>(src, dst, med, G, P, strip, strip < nstrips, ylo, yhi, my);
+    else
+        tb3_sweep<S, R, PN, false>(src, dst, med, G, P, strip, strip < nstrips, ylo, yhi, my);
 }
 
 // Maximum and minimum that propagate a NaN (fmax and fmin would drop it), so that a
@@ -356,11 +382,60 @@ int tb_resident(bool per_node_medium) {
                            : tb_resident_groups<S, R, false>();
 }
 
+// Work-groups of the three-step kernel resident on the device at once (0 if unknown).
+template <typename S, typename R, bool PN>
+int tb3_resident_groups() {
+    static const int n = [] {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tb3_step_kernel<S, R, PN>,
+                                                         64 * kTb3Waves, 0) != hipSuccess)
+            return 0;
+        return cus * per_cu;
+    }();
+    return n;
+}
+
+template <typename S, typename R>
+int tb3_resident(bool per_node_medium) {
+    return per_node_medium ? tb3_resident_groups<S, R, true>()
+                           : tb3_resident_groups<S, R, false>();
+}
+
+// Rows per segment of the three-step kernel (the last segment takes the rows left over, so none
+// has fewer), segments and work-groups per launch.  On a walled y axis there are at least two
+// segments, so that each walled end is where a segment's sweep starts.  A segment recomputes two
+// rows of step n+1 and one of step n+2 beyond each end, so it is at least kTb3MinRows high;
+// measured on the 4096^2 FP32 cavity, 16 rows (six rounds of the resident set) beat 8 and 32 by
+// 6 %, and on 2048^2, 8 rows beat 4 by 7 %.
+constexpr int kTb3Rounds = 6;
+constexpr int kTb3MinRows = 8;
+void tb3_shape_rows(const Geo& G, int resident, int* rows, int* nseg, int* nwg) {
+    const int nstrips = (G.nx + kTb3Cols - 1) / kTb3Cols;
+    const int ngrp = (nstrips + kTb3Waves - 1) / kTb3Waves;
+    const int want = resident > 0 ? max(1, kTb3Rounds * resident / ngrp) : 1;
+    int r = max(kTb3MinRows, (G.ny + want - 1) / want);
+    int n = max(1, G.ny / r);
+    if (G.wallS && n < 2) {
+        r = G.ny / 2;
+        n = 2;
+    }
+    *rows = r;
+    *nseg = n;
+    *nwg = ngrp * n;
+}
+
 // Queries the resident set of the two-step kernel once, outside any graph capture.
 template <typename S, typename R>
 void prepare_tb2() {
     (void)tb_resident<S, R>(true);
     (void)tb_resident<S, R>(false);
+    if constexpr (std::is_same<S, float>::value && std::is_same<R, float>::value) {
+        (void)tb3_resident<S, R>(true);
+        (void)tb3_resident<S, R>(false);
+    }
 }
 
 // Whether two steps per launch beat one.  Measured (fused / single MLUPS, per-node medium):
@@ -381,6 +456,25 @@ bool tb2_pays(const Geo& G, bool per_node_medium) {
         (long long)((nstrips + kTbWaves - 1) / kTbWaves) * ((G.ny + 15) / 16);
     if (resident <= 0) return false;
     return std::is_same<S, R>::value ? 4 * groups >= resident : groups >= 8LL * resident;
+}
+
+// Whether three steps per launch beat two (FP32 storage and arithmetic, a state below 2 GiB).
+// Measured (three / two steps per launch, FP32; per-node and uniform medium alike):
+//   4096^2 1.20 (16-row segments), 2048^2 1.02 (8 rows), 1024^2 0.82
+// (at 512^2 the tiles in LDS beat both).  It pays when segments of kTb3MinRows rows make at
+// least three rounds of the resident set.
+template <typename S, typename R>
+bool tb3_pays(const Geo& G, bool per_node_medium) {
+    if constexpr (std::is_same<S, float>::value && std::is_same<R, float>::value) {
+        if (tb2_descs(G, sizeof(S)) != 1) return false;
+        const int resident = tb3_resident<S, R>(per_node_medium);
+        if (resident <= 0) return false;
+        const long long ngrp = ((G.nx + kTb3Cols - 1) / kTb3Cols + kTb3Waves - 1) / kTb3Waves;
+        return ngrp * (G.ny / kTb3MinRows) >= 3LL * resident;
+    } else {
+        (void)G, (void)per_node_medium;
+        return false;
+    }
 }
 
 template <typename S, typename R>
@@ -413,6 +507,37 @@ hipError_t launch_tb2_step(const void* src, void* dst, const void* med, const Ge
         tb2_step_kernel<S, R, false, 2><<<nwg, 64 * kTbWaves, 0, s>>>(
             (const S*)src, (S*)dst, nullptr, G, P, nstrips, rows, chunk);
     return hipGetLastError();
+}
+
+template <typename S, typename R>
+void tb3_shape(const Geo& G, bool per_node_medium, int* rows, int* nseg, int* nwg) {
+    if constexpr (std::is_same<S, float>::value && std::is_same<R, float>::value)
+        tb3_shape_rows(G, tb3_resident<S, R>(per_node_medium), rows, nseg, nwg);
+    else
+        *rows = *nseg = *nwg = 0;
+}
+
+template <typename S, typename R>
+hipError_t launch_tb3_step(const void* src, void* dst, const void* med, const Geo& G,
+                           const Phys<R>& P, hipStream_t s) {
+    if constexpr (std::is_same<S, float>::value && std::is_same<R, float>::value) {
+        if (tb2_descs(G, sizeof(S)) != 1) return hipErrorInvalidValue;
+        const int nstrips = (G.nx + kTb3Cols - 1) / kTb3Cols;
+        int rows = 0, nseg = 0, nwg = 0;
+        tb3_shape<S, R>(G, med != nullptr, &rows, &nseg, &nwg);
+        if (G.wallS && (nseg < 2 || rows < 2)) return hipErrorInvalidValue;
+        const int chunk = max(1, tb3_resident<S, R>(med != nullptr) / 8);
+        if (med)
+            tb3_step_kernel<S, R, true><<<nwg, 64 * kTb3Waves, 0, s>>>(
+                (const S*)src, (S*)dst, (const S*)med, G, P, nstrips, rows, nseg, chunk);
+        else
+            tb3_step_kernel<S, R, false><<<nwg, 64 * kTb3Waves, 0, s>>>(
+                (const S*)src, (S*)dst, nullptr, G, P, nstrips, rows, nseg, chunk);
+        return hipGetLastError();
+    } else {
+        (void)src, (void)dst, (void)med, (void)G, (void)P, (void)s;
+        return hipErrorInvalidValue;
+    }
 }
 
 // parity 0: the state is in the kAAOpp form (even step count); 1: kAAOwn (odd)
@@ -518,6 +643,10 @@ hipError_t launch_pitch_copy(void* dst, const void* src, const Geo& G, double v,
     template void prepare_tb2<S, R>();                                                           \
     template bool tb2_pays<S, R>(const Geo&, bool);                                              \
     template void tb2_shape<S, R>(const Geo&, bool, int*, int*);                                 \
+    template bool tb3_pays<S, R>(const Geo&, bool);                                              \
+    template void tb3_shape<S, R>(const Geo&, bool, int*, int*, int*);                           \
+    template hipError_t launch_tb3_step<S, R>(const void*, void*, const void*, const Geo&,       \
+                                              const Phys<R>&, hipStream_t);                      \
     template hipError_t launch_observe<S, R>(const void*, const void*, const Geo&,               \
                                              const Phys<R>&, int, void*, void*, void*, void*,    \
                                              double*, int, double, double*, hipStream_t);        \

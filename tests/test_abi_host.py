@@ -171,11 +171,10 @@ def test_aa_layout_halves_the_state_memory(lbm):
 
 def test_aa_layout_limits(lbm):
     assert status_of(lbm, layout=3) == -1                          # LBM_E_INVAL
-    assert status_of(lbm, steps_per_launch=3) == -1
     assert status_of(lbm, steps_per_launch=4) == 0                 # 16 x 16 tiles in LDS
     assert status_of(lbm, steps_per_launch=8) == 0                 # 8 x 8 tiles in LDS
     assert status_of(lbm, steps_per_launch=5) == -1
-    assert status_of(lbm, steps_per_launch=3) == -1
+    assert status_of(lbm, steps_per_launch=6) == -1
     assert status_of(lbm, layout=1, checkpoint_every=10) == -6     # LBM_E_UNSUPPORTED: no tape
     from paper_1308_2071_amd import _abi
     p = (_abi.LbmParams * 1)(lbm.make_params(nx=16, ny=16, layout="aa"))
@@ -183,7 +182,17 @@ def test_aa_layout_limits(lbm):
     assert _abi.library().lbm_batch_workspace_size(1, p, C.byref(n)) == -6
 
 
-@pytest.mark.parametrize("spl", [4, 8])
+def test_three_steps_per_launch_need_fp32_and_a_state_below_2_gib(lbm):
+    assert status_of(lbm, steps_per_launch=3) == 0
+    assert status_of(lbm, dtype=1, steps_per_launch=3) == -6       # FP64: LBM_E_UNSUPPORTED
+    assert status_of(lbm, dtype=2, steps_per_launch=3) == -6       # FP32 storage, FP64 arithmetic
+    # 14 planes of pitch x ny + 1056 FP32 elements: 6100^2 holds 2.10e9 bytes, 6200^2 2.16e9
+    assert status_of(lbm, nx=6100, ny=6100, steps_per_launch=3) == 0
+    assert status_of(lbm, nx=6200, ny=6200, steps_per_launch=3) == -6
+    assert status_of(lbm, nx=6200, ny=6200, steps_per_launch=0) == 0    # two, on two descriptors
+
+
+@pytest.mark.parametrize("spl", [3, 4, 8])
 def test_a_batch_has_no_tile_form(lbm, spl):
     from paper_1308_2071_amd import _abi
     p = (_abi.LbmParams * 2)(lbm.make_params(nx=32, ny=32, steps_per_launch=spl),

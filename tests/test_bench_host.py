@@ -39,7 +39,8 @@ def test_traffic_is_read_only_while_the_sources_match(tmp_path, monkeypatch):
 def test_committed_profiles_name_the_roofline_kernels():
     for kernel, path in bench.TRAFFIC_PROFILES.items():
         assert os.path.exists(path), path
-        assert kernel in ("tb2_step_kernel<float,float,true>", "step_kernel<float,float,true>")
+        assert kernel in ("tb3_step_kernel<float,float,true>", "tb2_step_kernel<float,float,true>",
+                          "step_kernel<float,float,true>")
 
 
 def test_roofline_object_of_a_fused_run(monkeypatch):
@@ -64,6 +65,7 @@ def test_roofline_object_of_a_fused_run(monkeypatch):
 def test_kernel_names():
     assert bench.kernel_name("fp32", (1, 0, 0, 1)) == "step_kernel<float,float,true>"
     assert bench.kernel_name("fp32_f64", (2, 0, 12, 5)) == "tb2_step_kernel<float,double,true>"
+    assert bench.kernel_name("fp32", (3, 0, 16, 4608)) == "tb3_step_kernel<float,float,true>"
 
 
 def test_more_than_one_gpu_is_refused():

@@ -137,14 +137,16 @@ def test_roofline4096_crop512_2000_steps(dtype, spl):
 @pytest.mark.parametrize("dtype", ["fp32", "fp32_f64"])
 def test_roofline4096_fused_equals_single_steps_over_1000_steps(dtype):
     """The benchmark's launch configuration on the full field, beyond what the oracle reaches
-    there: the default time loop (two steps per launch on this grid) equals one step per launch
-    bitwise after 1000 steps, and after an odd count (a single step ends the run)."""
+    there: the default time loop (three steps per launch on this grid in FP32, two with FP64
+    arithmetic) equals one step per launch bitwise after 1000 steps, and after one more (a
+    single step ends the run)."""
     w = workloads.roofline4096()
     phi = torch.from_numpy(w["phi"].astype(np.float32))
     K = torch.from_numpy(w["K"].astype(np.float32))
     fused = Cavity(dict(w["params"], dtype=dtype), phi=phi, K=K)
     single = Cavity(dict(w["params"], dtype=dtype, steps_per_launch=1), phi=phi, K=K)
-    assert lbm_step_shape(fused.ctx)[0] == 2 and lbm_step_shape(single.ctx)[0] == 1
+    assert lbm_step_shape(fused.ctx)[0] == (3 if dtype == "fp32" else 2)
+    assert lbm_step_shape(single.ctx)[0] == 1
     for n in (1000, 1):
         fused.step(n)
         single.step(n)
