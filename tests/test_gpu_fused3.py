@@ -120,3 +120,18 @@ def test_roofline4096_three_steps_equal_single_steps():
         assert_same(a, b, f"after {n} more")
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("n,dtype,spl", [(4096, "fp32", 3), (3072, "fp32", 3), (2048, "fp32", 3),
+                                         (1536, "fp32", 2), (1024, "fp32", 2),
+                                         (4096, "fp64", 2), (4096, "fp32_f64", 2)])
+def test_default_form_by_grid(n, dtype, spl):
+    """The default time loop takes three steps per launch in FP32 where segments of 8 rows give
+    three rounds of the resident set (2048^2 and up on this device), else two on these grids;
+    FP64 arithmetic never takes three."""
+    tdt = torch.float64 if dtype == "fp64" else torch.float32
+    c = Cavity(dict(nx=n, ny=n, Ra=1e6, Pr=0.71, dtype=dtype), phi=torch.full((n, n), 0.6, dtype=tdt),
+               K=torch.full((n, n), 1.0, dtype=tdt))
+    shape = lbm_step_shape(c.ctx)
+    c.close()
+    assert shape[0] == spl, shape
