@@ -84,20 +84,21 @@ __global__ __launch_bounds__(64 * kTbWaves, (tb_min_waves<S, R>())) void tb2_ste
 // Three steps per launch (FP32): a work-group holds kTb3Waves adjacent strips of one row
 // segment, each with its own ring of step n+2 rows in LDS, kept in step by a barrier per row.
 // Segments alternate their sweep direction, except that the segment at a south wall sweeps
-// forwards and the one at a north wall backwards; the last segment takes the rows left over.
+// forwards and the one at a north wall backwards.  The nseg segments split the rows evenly
+// (their heights differ by one at most), so that no work-group runs longer than the others.
 template <typename S, typename R, bool PN>
 __global__ __launch_bounds__(64 * kTb3Waves, 3) void tb3_step_kernel(const S* __restrict__ src,
                                                                    S* __restrict__ dst,
                                                                    const S* __restrict__ med,
                                                                    Geo G, Phys<R> P, int nstrips,
-                                                                   int rows, int nseg,
-                                                                   int chunk) {
+                                                                   int nseg, int chunk) {
     __shared__ S ring[kTb3Waves * kTb3Ring];
     const int wg = tb_logical_group(chunk);
     const int ngrp = (nstrips + kTb3Waves - 1) / kTb3Waves;
     const int w = int(threadIdx.x) >> 6;
     const int strip = (wg % ngrp) * kTb3Waves + w, seg = wg / ngrp;
-    const int ylo = seg * rows, yhi = seg == nseg - 1 ? G.ny : ylo + rows;
+    const int ylo = int((long long)seg * G.ny / nseg);
+    const int yhi = int((long long)(seg + 1) * G.ny / nseg);
     const bool rev = (G.wallN && seg == nseg - 1) || (!(G.wallS && seg == 0) && (seg & 1));
     S* const my = ring + w * kTb3Ring;
     if (rev)
@@ -404,25 +405,22 @@ int tb3_resident(bool per_node_medium) {
                            : tb3_resident_groups<S, R, false>();
 }
 
-// Rows per segment of the three-step kernel (the last segment takes the rows left over, so none
-// has fewer), segments and work-groups per launch.  On a walled y axis there are at least two
-// segments, so that each walled end is where a segment's sweep starts.  A segment recomputes two
-// rows of step n+1 and one of step n+2 beyond each end, so it is at least kTb3MinRows high;
-// measured on the 4096^2 FP32 cavity, 16 rows (six rounds of the resident set) beat 8 and 32 by
-// 6 %, and on 2048^2, 8 rows beat 4 by 7 %.
+// Rows per segment of the three-step kernel (the least height: the segments split the rows
+// evenly, so some take one more), segments and work-groups per launch.  On a walled y axis there
+// are at least two segments, so that each walled end is where a segment's sweep starts.  A
+// segment recomputes two rows of step n+1 and one of step n+2 beyond each end, so it is at least
+// kTb3MinRows high; measured on the 4096^2 FP32 cavity, 16 rows (six rounds of the resident set)
+// beat 8 and 32 by 6 %, and on 2048^2, 8 rows beat 4 by 7 %.
 constexpr int kTb3Rounds = 6;
 constexpr int kTb3MinRows = 8;
 void tb3_shape_rows(const Geo& G, int resident, int* rows, int* nseg, int* nwg) {
     const int nstrips = (G.nx + kTb3Cols - 1) / kTb3Cols;
     const int ngrp = (nstrips + kTb3Waves - 1) / kTb3Waves;
     const int want = resident > 0 ? max(1, kTb3Rounds * resident / ngrp) : 1;
-    int r = max(kTb3MinRows, (G.ny + want - 1) / want);
+    const int r = max(kTb3MinRows, (G.ny + want - 1) / want);
     int n = max(1, G.ny / r);
-    if (G.wallS && n < 2) {
-        r = G.ny / 2;
-        n = 2;
-    }
-    *rows = r;
+    if (G.wallS && n < 2) n = 2;
+    *rows = G.ny / n;
     *nseg = n;
     *nwg = ngrp * n;
 }
@@ -525,14 +523,17 @@ hipError_t launch_tb3_step(const void* src, void* dst, const void* med, const Ge
         const int nstrips = (G.nx + kTb3Cols - 1) / kTb3Cols;
         int rows = 0, nseg = 0, nwg = 0;
         tb3_shape<S, R>(G, med != nullptr, &rows, &nseg, &nwg);
-        if (G.wallS && (nseg < 2 || rows < 2)) return hipErrorInvalidValue;
+        // every segment holds at least one row (its sweep loop runs until it passes the last),
+        // and on a walled y axis two segments of at least two
+        if (nseg < 1 || nseg > G.ny || (G.wallS && (nseg < 2 || rows < 2)))
+            return hipErrorInvalidValue;
         const int chunk = max(1, tb3_resident<S, R>(med != nullptr) / 8);
         if (med)
             tb3_step_kernel<S, R, true><<<nwg, 64 * kTb3Waves, 0, s>>>(
-                (const S*)src, (S*)dst, (const S*)med, G, P, nstrips, rows, nseg, chunk);
+                (const S*)src, (S*)dst, (const S*)med, G, P, nstrips, nseg, chunk);
         else
             tb3_step_kernel<S, R, false><<<nwg, 64 * kTb3Waves, 0, s>>>(
-                (const S*)src, (S*)dst, nullptr, G, P, nstrips, rows, nseg, chunk);
+                (const S*)src, (S*)dst, nullptr, G, P, nstrips, nseg, chunk);
         return hipGetLastError();
     } else {
         (void)src, (void)dst, (void)med, (void)G, (void)P, (void)s;
