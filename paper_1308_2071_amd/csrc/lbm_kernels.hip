@@ -84,21 +84,22 @@ __global__ __launch_bounds__(64 * kTbWaves, (tb_min_waves<S, R>())) void tb2_ste
 // Three steps per launch (FP32): a work-group holds kTb3Waves adjacent strips of one row
 // segment, each with its own ring of step n+2 rows in LDS, kept in step by a barrier per row.
 // Segments alternate their sweep direction, except that the segment at a south wall sweeps
-// forwards and the one at a north wall backwards.  The nseg segments split the rows evenly
-// (their heights differ by one at most), so that no work-group runs longer than the others.
+// forwards and the one at a north wall backwards.  The nseg segments split the rows evenly: the
+// first `extra` have rows + 1 rows, the others rows, so that no work-group runs long.
 template <typename S, typename R, bool PN>
 __global__ __launch_bounds__(64 * kTb3Waves, 3) void tb3_step_kernel(const S* __restrict__ src,
                                                                    S* __restrict__ dst,
                                                                    const S* __restrict__ med,
                                                                    Geo G, Phys<R> P, int nstrips,
-                                                                   int nseg, int chunk) {
+                                                                   int rows, int extra, int nseg,
+                                                                   int chunk) {
     __shared__ S ring[kTb3Waves * kTb3Ring];
     const int wg = tb_logical_group(chunk);
     const int ngrp = (nstrips + kTb3Waves - 1) / kTb3Waves;
     const int w = int(threadIdx.x) >> 6;
     const int strip = (wg % ngrp) * kTb3Waves + w, seg = wg / ngrp;
-    const int ylo = int((long long)seg * G.ny / nseg);
-    const int yhi = int((long long)(seg + 1) * G.ny / nseg);
+    const int ylo = seg * rows + min(seg, extra);
+    const int yhi = ylo + rows + (seg < extra ? 1 : 0);
     const bool rev = (G.wallN && seg == nseg - 1) || (!(G.wallS && seg == 0) && (seg & 1));
     S* const my = ring + w * kTb3Ring;
     if (rev)
@@ -527,13 +528,14 @@ hipError_t launch_tb3_step(const void* src, void* dst, const void* med, const Ge
         // and on a walled y axis two segments of at least two
         if (nseg < 1 || nseg > G.ny || (G.wallS && (nseg < 2 || rows < 2)))
             return hipErrorInvalidValue;
+        const int extra = G.ny - rows * nseg;   // segments one row taller
         const int chunk = max(1, tb3_resident<S, R>(med != nullptr) / 8);
         if (med)
             tb3_step_kernel<S, R, true><<<nwg, 64 * kTb3Waves, 0, s>>>(
-                (const S*)src, (S*)dst, (const S*)med, G, P, nstrips, nseg, chunk);
+                (const S*)src, (S*)dst, (const S*)med, G, P, nstrips, rows, extra, nseg, chunk);
         else
             tb3_step_kernel<S, R, false><<<nwg, 64 * kTb3Waves, 0, s>>>(
-                (const S*)src, (S*)dst, nullptr, G, P, nstrips, nseg, chunk);
+                (const S*)src, (S*)dst, nullptr, G, P, nstrips, rows, extra, nseg, chunk);
         return hipGetLastError();
     } else {
         (void)src, (void)dst, (void)med, (void)G, (void)P, (void)s;
