@@ -63,7 +63,7 @@ def test_aa_equals_pull_bitwise(bc, shape, dtype):
 
 @pytest.mark.parametrize("dtype", ["fp32", "fp64"])
 def test_aa_graph_replay_and_uniform_medium(dtype):
-    """Long runs replay a captured graph of 64 alternating launches; 131 steps = two graphs
+    """Long runs replay a captured graph of 48 alternating launches; 131 steps = two graphs
     plus an odd remainder.  Uniform medium: no medium planes."""
     params = dict(nx=70, ny=44, Ra=1e5, Pr=1.0, Da=2e-2)
     a, b = pair(params, dtype, phi_u=0.45)

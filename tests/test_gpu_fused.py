@@ -66,7 +66,7 @@ def test_two_steps_per_launch_equal_single_steps(bc, shape, dtype):
 def test_fused_graph_replay_uniform_medium_and_heat_source(dtype):
     params = dict(nx=200, ny=150, Ra=1e5, Ra_I=1e5, Pr=0.7, Da=1e-2)
     a, b = pair(params, dtype, phi_u=0.4)
-    a.step(257)            # graphs of 64 steps (32 fused launches) and an odd remainder
+    a.step(257)            # graphs of 48 steps (24 fused launches) and an odd remainder
     b.step(257)
     assert_same(a, b, "257 steps")
     a.close()

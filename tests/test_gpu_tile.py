@@ -76,7 +76,7 @@ def test_steps_in_lds_equal_single_steps(bc, shape, dtype, spl):
 def test_tile_graph_replay_uniform_medium_and_heat_source(dtype, spl):
     params = dict(nx=200, ny=150, Ra=1e5, Ra_I=1e5, Pr=0.7, Da=1e-2)
     a, b = pair(params, dtype, phi_u=0.4, spl=spl)
-    a.step(259)            # graphs of 64 steps (64 / spl launches) and a remainder of 3
+    a.step(259)            # graphs of 48 steps (48 / spl launches); of the 19 left, 3 single
     b.step(259)
     assert_same(a, b, "259 steps")
     a.close()
