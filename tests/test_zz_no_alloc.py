@@ -47,13 +47,16 @@ def assert_same(a, b, what):
 
 CASES = [
     # per-node medium, FP64, mixed walls; then a smaller uniform FP32 cavity, odd step count;
-    # then two steps per launch forced on a mid-size FP32 cavity
+    # then two and three steps per launch forced on mid-size FP32 cavities (65 steps: 21 launches
+    # of three and two single steps)
     ("per_node_fp64", dict(nx=300, ny=200, Ra=1e5, Pr=0.71, dtype="fp64",
                            bc=(1, 0, 0, 1), T_wall=(0.0, 0.2, 1.0, 0.0)), True, 0.6, 500),
     ("uniform_fp32", dict(nx=64, ny=48, Ra=1e4, Pr=1.0, Da=1e-2, dtype="fp32"), False, 0.45,
      301),
     ("fused_fp32", dict(nx=600, ny=400, Ra=1e6, Pr=0.71, dtype="fp32", steps_per_launch=2),
      True, 0.6, 64),
+    ("fused3_fp32", dict(nx=500, ny=300, Ra=1e6, Pr=0.71, dtype="fp32", steps_per_launch=3,
+                         bc=(0, 0, 1, 0), T_wall=(1.0, 0.0, 0.0, 0.4)), True, 0.6, 65),
 ]
 
 
